@@ -1,0 +1,179 @@
+"""Seeded synthetic inputs for the stencil workloads.
+
+This module only draws numbers and lays them out; it holds none of the
+stencils' arithmetic, so both the HIP path (tests, benchmark) and the CPU
+oracle can be fed from it without sharing any computation.
+
+Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014) used in counter form: the value
+for linear index ``idx`` of stream ``stream`` under ``seed`` is the SplitMix64
+output function applied to ``key + (idx + 1) * GAMMA`` with
+``key = seed * 2**16 + stream`` and GAMMA the golden-ratio increment.  A
+uniform double in [0, 1) is ``(x >> 11) * 2**-53``.  Linear indices run over
+the PADDED array, so a value does not depend on the chunking used here.
+
+Workload recipes (padded layout: x contiguous, halo r on every side):
+
+* heat2d5: 256 x 256 interior, 1-cell ring fixed at 0, u0 = U[0,1)
+  (seed 1, stream 0), coefficients 0.6 centre / 0.1 per neighbour, T = 10.
+* poisson19: 129 x 129 x 257 grid INCLUDING its 1-cell boundary (interior
+  127 x 127 x 255), FP32 arrays a0..a2 = 1, a3 = fl32(1/6), b0..b2 = 0,
+  c0..c2 = 1, bnd = 1, wrk1 = 0; p = k^2 / 256^2 with k the z storage index
+  (boundary included); omega = 0.8; T = 20.
+* wave25: 512^3 interior + 4-cell halo; v = 1.5 + 3 U (seed 3, stream 0),
+  vsq = (v * 0.4 / 4.5)^2 (Courant number at most 0.4); both time levels
+  u^{-1} = u^0 = 1 + 0.1 U (seed 3, stream 1) over the whole padded array;
+  per-axis coefficients (-2.847222, 1.6, -0.2, 0.025397, -0.001786); T = 10.
+* heat3d7 batch: 64 problems, interior edges nx, ny, nz each drawn
+  independently as 32 + floor(129 U) (seed 4, stream 0, problem-major), fields
+  U[0,1) (seed 4, stream 1 + b) with a 0 ring; coefficients 0.4 / 0.1; T = 50.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_CHUNK = 1 << 22
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    z = (z ^ (z >> np.uint64(30))) * _M1
+    z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def splitmix64(seed: int, stream: int, start: int, count: int) -> np.ndarray:
+    """Raw 64-bit outputs for linear indices start .. start+count-1."""
+    key = np.uint64((int(seed) << 16) + int(stream))
+    idx = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return _mix64(key + idx * GAMMA)
+
+
+def uniform_f64(seed: int, stream: int, shape) -> np.ndarray:
+    """U[0,1) doubles, (x >> 11) * 2^-53, filled in index order."""
+    n = int(np.prod(shape))
+    out = np.empty(n, dtype=np.float64)
+    for s in range(0, n, _CHUNK):
+        c = min(_CHUNK, n - s)
+        out[s:s + c] = (splitmix64(seed, stream, s, c) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    return out.reshape(shape)
+
+
+def uniform_f32(seed: int, stream: int, shape) -> np.ndarray:
+    """U[0,1) floats, (x >> 40) * 2^-24 (exact in FP32)."""
+    n = int(np.prod(shape))
+    out = np.empty(n, dtype=np.float32)
+    for s in range(0, n, _CHUNK):
+        c = min(_CHUNK, n - s)
+        out[s:s + c] = ((splitmix64(seed, stream, s, c) >> np.uint64(40)).astype(np.float64)
+                        * (2.0 ** -24)).astype(np.float32)
+    return out.reshape(shape)
+
+
+def zero_halo(a: np.ndarray, r: int) -> np.ndarray:
+    """Set the halo of width r of a padded array to 0 (in place)."""
+    for ax in range(a.ndim):
+        sl = [slice(None)] * a.ndim
+        sl[ax] = slice(0, r)
+        a[tuple(sl)] = 0
+        sl[ax] = slice(a.shape[ax] - r, a.shape[ax])
+        a[tuple(sl)] = 0
+    return a
+
+
+# --------------------------------------------------------------------------
+# heat2d5: 2-D five-point Jacobi heat sweep
+HEAT2D5 = dict(n=256, T=10, cc=0.6, cn=0.1, seed=1)
+
+
+def heat2d5_input(n: int = 256, seed: int = 1, stream: int = 0, ny: int | None = None) -> np.ndarray:
+    ny = n if ny is None else ny
+    u = uniform_f64(seed, stream, (ny + 2, n + 2))
+    return zero_halo(u, 1)
+
+
+# --------------------------------------------------------------------------
+# heat3d7: 3-D seven-point Jacobi heat sweep, batch of uneven grids
+HEAT3D7 = dict(count=64, lo=32, hi=160, T=50, cc=0.4, cn=0.1, seed=4)
+
+
+def heat3d7_batch_sizes(count: int = 64, seed: int = 4, lo: int = 32, hi: int = 160):
+    """Interior (nx, ny, nz) per problem, each edge lo + floor((hi-lo+1) U)."""
+    u = uniform_f64(seed, 0, (count * 3,))
+    e = lo + np.floor(u * (hi - lo + 1)).astype(np.int64)
+    return [tuple(int(v) for v in e[3 * b:3 * b + 3]) for b in range(count)]
+
+
+def heat3d7_input(nx: int, ny: int, nz: int, seed: int = 4, stream: int = 1) -> np.ndarray:
+    u = uniform_f64(seed, stream, (nz + 2, ny + 2, nx + 2))
+    return zero_halo(u, 1)
+
+
+# --------------------------------------------------------------------------
+# poisson19: 19-point variable-coefficient pressure relaxation (FP32 storage)
+POISSON19 = dict(shape_total=(257, 129, 129), omega=0.8, T=20)
+POISSON_COEF_ORDER = ("a0", "a1", "a2", "a3", "b0", "b1", "b2", "c0", "c1", "c2", "bnd", "wrk1")
+POISSON_COEF_VALUES = dict(a0=1.0, a1=1.0, a2=1.0, a3=1.0 / 6.0, b0=0.0, b1=0.0, b2=0.0,
+                           c0=1.0, c1=1.0, c2=1.0, bnd=1.0, wrk1=0.0)
+
+
+def poisson19_inputs(shape_total=(257, 129, 129), values=None):
+    """p and the 12 coefficient arrays as FP32 padded grids (z, y, x), the
+    given shape including the 1-cell boundary.  p = k^2/(K-1)^2 with k the z
+    storage index and K the z extent (exact in FP32 for K = 257)."""
+    vals = dict(POISSON_COEF_VALUES)
+    if values:
+        vals.update(values)
+    K = shape_total[0]
+    k = np.arange(K, dtype=np.float64)
+    prof = (k * k / float((K - 1) ** 2)).astype(np.float32)
+    p = np.empty(shape_total, dtype=np.float32)
+    p[...] = prof[:, None, None]
+    coefs = [np.full(shape_total, np.float32(vals[name]), dtype=np.float32) for name in POISSON_COEF_ORDER]
+    return p, coefs
+
+
+def poisson19_random_inputs(shape_total, seed: int = 7):
+    """A dense variant with every coefficient array random (for parity of
+    every term, including the b cross terms that are 0 in the workload above):
+    a*, c* in [0.5, 1.5), b* in [-0.25, 0.25), a3 in [0.1, 0.2), bnd in
+    {0, 1}, wrk1 in [-0.01, 0.01), p in [0, 1).  Streams 0..12."""
+    p = uniform_f32(seed, 0, shape_total)
+    coefs = []
+    for s, name in enumerate(POISSON_COEF_ORDER):
+        u = uniform_f32(seed, 1 + s, shape_total)
+        if name in ("a0", "a1", "a2", "c0", "c1", "c2"):
+            c = np.float32(0.5) + u
+        elif name in ("b0", "b1", "b2"):
+            c = (u - np.float32(0.5)) * np.float32(0.5)
+        elif name == "a3":
+            c = np.float32(0.1) + u * np.float32(0.1)
+        elif name == "bnd":
+            c = (u < np.float32(0.9)).astype(np.float32)
+        else:
+            c = (u - np.float32(0.5)) * np.float32(0.02)
+        coefs.append(np.ascontiguousarray(c, dtype=np.float32))
+    return p, coefs
+
+
+# --------------------------------------------------------------------------
+# wave25: radius-4 25-point leapfrog wave update
+WAVE25 = dict(n=512, T=10, seed=3)
+WAVE25_COEF = (-2.847222, 1.6, -0.2, 0.025397, -0.001786)
+WAVE25_COURANT_DT_OVER_H = 0.4 / 4.5
+
+
+def wave25_inputs(nx: int, ny: int | None = None, nz: int | None = None, seed: int = 3):
+    """(u_prev, u_cur, vsq) float64 padded grids with a 4-cell halo."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    shape = (nz + 8, ny + 8, nx + 8)
+    v = 1.5 + 3.0 * uniform_f64(seed, 0, shape)
+    vsq = v * WAVE25_COURANT_DT_OVER_H
+    vsq *= vsq
+    del v
+    u = 1.0 + 0.1 * uniform_f64(seed, 1, shape)
+    return u, u.copy(), vsq
