@@ -1,0 +1,271 @@
+"""Benchmark: grid-point updates/s of the stencil sweeps on one MI355X.
+
+Default workload: the 19-point variable-coefficient pressure relaxation on a
+129 x 129 x 257 grid (boundary included; interior 127 x 127 x 255), F32
+storage with FP64 arithmetic and FP64 residual, omega 0.8, 20 sweeps per
+step, saturated form (the plain form is timed beside it).  One step = one
+stencil_run of 20 sweeps plus the residual read-back.  Inputs are resident
+in HBM before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.  Other workloads (--workload wave25 | heat2d5 |
+heat3d7) exist for profiling runs of their kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+
+
+def sha256_of(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def read_traffic(kernel_tag: str, source: str):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, or None
+    when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != sha256_of(os.path.join(ROOT, "paper_2306_13002_amd", "csrc", source)):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def setup_workload(name, variant, dev, torch, synth, Plan):
+    """Returns (plan, run_step, points_per_step, sweeps_per_step, meta)."""
+    if name == "poisson19":
+        p0, cf = synth.poisson19_inputs()
+        n = (127, 127, 255)
+        plan = Plan("poisson19", n, variant=variant, omega=0.8)
+        f = [torch.tensor(p0, device=dev), torch.empty(p0.shape, dtype=torch.float32, device=dev)]
+        cs = [torch.tensor(c, device=dev) for c in cf]
+        base = f[0].clone()
+        T = 20
+
+        def step():
+            plan.run(f, cs, iterations=T)
+            return plan.residual()
+
+        def reset():
+            f[0].copy_(base)
+
+        meta = dict(workload="poisson19 19-point variable-coefficient pressure relaxation, 129x129x257 incl. "
+                             "boundary, F32 storage / FP64 arithmetic, omega 0.8, 20 sweeps + FP64 residual",
+                    grid_total=[129, 129, 257], interior=list(n), iterations=T, bytes_per_update=56,
+                    kernel_tag="poisson19_sat_129x129x257" if variant == "saturated" else "poisson19_plain_129x129x257",
+                    source="poisson19.hip", storage="f32")
+        return plan, step, reset, n[0] * n[1] * n[2] * T, T, meta
+    if name == "wave25":
+        a, b, v = synth.wave25_inputs(512)
+        n = (512, 512, 512)
+        plan = Plan("wave25", n, variant=variant, coef=synth.WAVE25_COEF)
+        f = [torch.tensor(a, device=dev), torch.tensor(b, device=dev)]
+        vs = [torch.tensor(v, device=dev)]
+        del a, b, v
+        T = 10
+
+        def step():
+            plan.run(f, vs, iterations=T)
+            return plan.residual()
+
+        meta = dict(workload="wave25 radius-4 leapfrog, 512^3 interior + 4-cell halo, FP64, 10 steps + residual",
+                    interior=list(n), iterations=T, bytes_per_update=32,
+                    kernel_tag=f"wave25_{'sat' if variant == 'saturated' else 'plain'}_512c", source="wave25.hip",
+                    storage="f64")
+        return plan, step, (lambda: None), n[0] * n[1] * n[2] * T, T, meta
+    if name in ("heat2d5", "heat3d7"):
+        if name == "heat2d5":
+            u0 = synth.heat2d5_input(256)
+            n, T, coef = (256, 256), 10, (0.6, 0.1)
+        else:
+            n, T, coef = (160, 160, 160), 50, (0.4, 0.1)
+            u0 = synth.heat3d7_input(*n)
+        plan = Plan(name, n, variant=variant if name == "heat3d7" else "plain", coef=coef)
+        f = [torch.tensor(u0, device=dev), torch.empty(u0.shape, dtype=torch.float64, device=dev)]
+        base = f[0].clone()
+
+        def step():
+            plan.run(f, iterations=T)
+            return plan.residual()
+
+        def reset():
+            f[0].copy_(base)
+
+        pts = 1
+        for v in n:
+            pts *= v
+        meta = dict(workload=f"{name} Jacobi heat, interior {n}, FP64, {T} sweeps + residual", interior=list(n),
+                    iterations=T, bytes_per_update=16, kernel_tag=f"{name}_{variant}", source="heat.hip",
+                    storage="f64")
+        return plan, step, reset, pts * T, T, meta
+    raise SystemExit(f"unknown workload {name}")
+
+
+def time_variant(name, variant, steps, warmup, dev, torch, synth, Plan):
+    plan, step, reset, pts, T, meta = setup_workload(name, variant, dev, torch, synth, Plan)
+    plan.profile(True)
+    for _ in range(warmup):
+        reset()
+        step()
+    torch.cuda.synchronize()
+    sweep_ms = 0.0
+    sweeps = 0
+    resid = None
+    # The reset copy (poisson19/heat) restores the initial state so every step
+    # does identical work; it is a plain device copy outside the sweeps and is
+    # included in the wall time.
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        reset()
+        resid = step()
+        ms, n = plan.profile_read()
+        sweep_ms += ms
+        sweeps += n
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cfg = plan.config()
+    plan.close()
+    return dict(wall=wall, pts=pts, sweep_ms=sweep_ms, sweeps=sweeps, resid=resid, meta=meta, cfg=cfg, T=T)
+
+
+def cpu_baseline(name):
+    """Time the CPU oracle (single thread, as written) on a bounded sample."""
+    import numpy as np
+
+    import oracle
+    from paper_2306_13002_amd import synth
+
+    if name == "poisson19":
+        p0, cf = synth.poisson19_inputs()
+        t = time.perf_counter()
+        oracle.poisson19(p0, cf, 0.8, 2, mode="F32STORE")
+        one = (time.perf_counter() - t) / 2
+        k = max(2, min(100, int(10.0 / max(one, 1e-3))))
+        t = time.perf_counter()
+        oracle.poisson19(p0, cf, 0.8, k, mode="F32STORE")
+        dt = time.perf_counter() - t
+        pts = 127 * 127 * 255 * k
+        return dict(value=pts / dt, unit="grid-point updates/s", cores=1, kind="oracle",
+                    sample=f"full 129x129x257 grid, {k} sweeps (F32STORE mode), {dt:.1f} s, single thread")
+    if name == "wave25":
+        a, b, v = synth.wave25_inputs(128, 128, 128)
+        t = time.perf_counter()
+        oracle.wave25(a, b, v, synth.WAVE25_COEF, 2)
+        one = (time.perf_counter() - t) / 2
+        k = max(1, min(50, int(10.0 / max(one, 1e-3))))
+        t = time.perf_counter()
+        oracle.wave25(a, b, v, synth.WAVE25_COEF, k)
+        dt = time.perf_counter() - t
+        return dict(value=128 ** 3 * k / dt, unit="grid-point updates/s", cores=1, kind="oracle",
+                    sample=f"128^3 crop of the same recipe, {k} steps, {dt:.1f} s, single thread")
+    u0 = synth.heat3d7_input(96, 96, 96) if name == "heat3d7" else synth.heat2d5_input(256)
+    t = time.perf_counter()
+    k = 20
+    oracle.heat(u0, k, 0.4, 0.1)
+    dt = time.perf_counter() - t
+    pts = int(np.prod([s - 2 for s in u0.shape])) * k
+    return dict(value=pts / dt, unit="grid-point updates/s", cores=1, kind="oracle",
+                sample=f"{u0.shape} padded grid, {k} sweeps, {dt:.1f} s, single thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="poisson19", choices=["poisson19", "wave25", "heat2d5", "heat3d7"])
+    ap.add_argument("--variant", default="saturated", choices=["saturated", "plain"])
+    ap.add_argument("--no-plain", action="store_true", help="skip timing the plain form beside it")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {a.gpus} requested); the stencil library has no "
+              "multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2306_13002_amd import synth
+    from paper_2306_13002_amd.stencil import Plan
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    main_r = time_variant(a.workload, a.variant, a.steps, a.warmup, dev, torch, synth, Plan)
+    meta = main_r["meta"]
+    value = main_r["pts"] * a.steps / main_r["wall"]
+    ms_per_step = main_r["wall"] * 1000.0 / a.steps
+    launch_s = main_r["sweep_ms"] / 1000.0 / max(1, main_r["sweeps"])
+    pts_per_launch = main_r["pts"] / main_r["T"]
+    alg_bytes = meta["bytes_per_update"] * pts_per_launch
+    achieved = alg_bytes / launch_s / 1e9
+    traffic = read_traffic(meta["kernel_tag"], meta["source"])
+    out = {
+        "metric": "grid-point updates/s (+ % of HBM peak), saturated vs plain",
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded recipe of the workload)",
+        "config": {
+            "workload": meta["workload"],
+            "variant": a.variant,
+            "tile": list(main_r["cfg"]["tile"]),
+            "interior": meta["interior"],
+            "iterations_per_step": meta["iterations"],
+            "storage": meta["storage"],
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": meta["kernel_tag"],
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "avg_launch_us": launch_s * 1e6,
+        },
+        "residual": main_r["resid"],
+    }
+    if not a.no_plain and a.variant == "saturated" and a.workload != "heat2d5":
+        pr = time_variant(a.workload, "plain", a.steps, a.warmup, dev, torch, synth, Plan)
+        pv = pr["pts"] * a.steps / pr["wall"]
+        pl = pr["sweep_ms"] / 1000.0 / max(1, pr["sweeps"])
+        out["plain"] = {"value": pv, "ms_per_step": pr["wall"] * 1000.0 / a.steps,
+                        "achieved_gbs": alg_bytes / pl / 1e9, "avg_launch_us": pl * 1e6,
+                        "tile": list(pr["cfg"]["tile"])}
+        out["saturated_over_plain"] = value / pv
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(a.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * stencil.h -- C ABI of the MI355X stencil-sweep library (libstencil.so).
+ *
+ * The library runs structured-grid stencil sweeps -- the data-parallel
+ * innermost loop bodies that ACC Saturator (arXiv 2306.13002) rewrites --
+ * as hand-written HIP kernels for gfx950, each in two forms:
+ *
+ *   STENCIL_PLAIN      the loop body translated directly: one thread per
+ *                      point, every operand loaded from memory, terms added
+ *                      in the written order (the paper's "original" code);
+ *   STENCIL_SATURATED  the body after the paper's rewrites (Sec. "Rewriting
+ *                      Rules", Sec. "Code Generation"): common subexpressions
+ *                      shared, shared coefficients factored, FMA chains,
+ *                      constants folded, temporaries kept in registers, loads
+ *                      issued early ("bulk load") and reused along the z axis
+ *                      through a register queue and LDS-staged xy tiles.
+ *
+ * Memory layout (every kind): a padded grid, x contiguous.  Element (x,y,z)
+ * of the padded grid is at  base + z*pitch_z + y*pitch_y + x  (elements);
+ * the interior point (i,j,k), 0 <= i < n[0], ... sits at (i+r, j+r, k+r)
+ * where r is the halo width.  pitch_y >= n[0]+2r, pitch_z >= pitch_y*(n[1]+2r);
+ * 0 selects the dense pitch.  2-D kinds ignore z.  The halo holds boundary
+ * values; under STENCIL_BC_DIRICHLET it is never written.
+ *
+ * Ownership: every grid pointer is a DEVICE pointer owned by the caller; the
+ * library never frees or reallocates caller memory.  Arrays in the descriptor
+ * (coef, tap_off, tap_cid) are HOST pointers, copied at plan time.  A plan
+ * owns only small device buffers (residual partials, tap tables, graphs),
+ * released by stencil_destroy.
+ *
+ * Errors: every entry returns a stencil_status.  All validation happens
+ * before anything is enqueued; on error nothing is enqueued, output handles
+ * are left NULL and stencil_last_error() (thread-local, never NULL)
+ * describes the failure.  Launch failures map to STENCIL_E_DEVICE.  The
+ * library never aborts and prints nothing unless STENCIL_LOG is set.
+ *
+ * Streams: a `stream` argument is a hipStream_t passed as void* (NULL = the
+ * null stream).  stencil_run is asynchronous; stencil_residual synchronizes
+ * the stream it is given, which must be the stream of the preceding run (or
+ * ordered after it).  Calls that share one plan must not overlap.
+ */
+#ifndef STENCIL_H
+#define STENCIL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stencil_plan_s *stencil_plan_t;
+
+typedef enum {
+    STENCIL_OK = 0,
+    STENCIL_E_INVAL = -1,       /* bad descriptor or argument */
+    STENCIL_E_UNSUPPORTED = -2, /* valid but not offered (kind/dtype/bc/tile combination) */
+    STENCIL_E_NOMEM = -3,       /* host or device allocation failed */
+    STENCIL_E_DEVICE = -4,      /* no usable GPU, or a HIP call/launch failed */
+    STENCIL_E_STATE = -5        /* call out of order (e.g. residual before any sweep) */
+} stencil_status;
+
+/* Stencil kinds.  Definitions per interior point (src -> dst):
+ *
+ * HEAT2D5   dst = c[0]*u + c[1]*u(-x) + c[1]*u(+x) + c[1]*u(-y) + c[1]*u(+y);
+ *           r = 1, F64; coef = {centre, neighbour}.  Jacobi heat sweep, the
+ *           paper's Jacobi class ("ostencil" in its SPEC ACCEL table).
+ * HEAT3D7   the same with -z, +z added; r = 1, F64.
+ * POISSON19 19-point variable-coefficient pressure relaxation (the halo-3D
+ *           CFD class of the paper's NPB/SPEC tables), F32 storage, FP64
+ *           arithmetic, r = 1, with (i,j,k) = (x,y,z) and every coefficient
+ *           read at the point itself:
+ *             s0 = a0*p(i+1,j,k) + a1*p(i,j+1,k) + a2*p(i,j,k+1)
+ *                + b0*(p(i+1,j+1,k) - p(i+1,j-1,k) - p(i-1,j+1,k) + p(i-1,j-1,k))
+ *                + b1*(p(i,j+1,k+1) - p(i,j-1,k+1) - p(i,j+1,k-1) + p(i,j-1,k-1))
+ *                + b2*(p(i+1,j,k+1) - p(i-1,j,k+1) - p(i+1,j,k-1) + p(i-1,j,k-1))
+ *                + c0*p(i-1,j,k) + c1*p(i,j-1,k) + c2*p(i,j,k-1) + wrk1
+ *             ss = (s0*a3 - p)*bnd ;  p' = p + omega*ss ;  residual = sum ss^2.
+ * WAVE25    radius-4 star, second order in time (leapfrog), F64, r = 4:
+ *             L(u) = sum over x,y,z of [c0*u + sum_{q=1..4} c_q*(u(+q) + u(-q))]
+ *             u_next = 2u - u_prev + vsq*L(u);   coef = {c0,c1,c2,c3,c4}.
+ * GENERIC   u'(x) = sum_t coef[cid_t] * u(x + delta_t), 3-D, radius 1..4,
+ *           F32 or F64, taps given by tap_off/tap_cid.
+ */
+typedef enum {
+    STENCIL_HEAT2D5 = 1,
+    STENCIL_HEAT3D7 = 2,
+    STENCIL_POISSON19 = 3,
+    STENCIL_WAVE25 = 4,
+    STENCIL_GENERIC = 5
+} stencil_kind;
+
+typedef enum { STENCIL_F32 = 1, STENCIL_F64 = 2 } stencil_dtype; /* storage type */
+typedef enum { STENCIL_PLAIN = 0, STENCIL_SATURATED = 1, STENCIL_AUTO = 2 } stencil_variant;
+/* How a plan picks variant and tile when variant == AUTO or a tile field is 0:
+ * FIXED uses library defaults; EXHAUSTIVE times every candidate on the device
+ * (results cached per size class); MODEL asks the learned cost model. */
+typedef enum { STENCIL_TUNE_FIXED = 0, STENCIL_TUNE_EXHAUSTIVE = 1, STENCIL_TUNE_MODEL = 2 } stencil_tune;
+/* DIRICHLET: halo fixed.  PERIODIC (heat kinds): before every sweep the halo
+ * is filled from the opposite side of the interior (the halo is written). */
+typedef enum { STENCIL_BC_DIRICHLET = 0, STENCIL_BC_PERIODIC = 1 } stencil_bc;
+
+typedef struct {
+    uint32_t struct_size;   /* = sizeof(stencil_desc) (ABI versioning) */
+    int32_t kind;           /* stencil_kind */
+    int32_t dtype;          /* stencil_dtype */
+    int32_t variant;        /* stencil_variant */
+    int32_t tune;           /* stencil_tune */
+    int32_t bc;             /* stencil_bc */
+    int32_t ndim;           /* 2 (HEAT2D5) or 3 */
+    int32_t radius;         /* halo width: 1 (heat, poisson19), 4 (wave25), 1..4 (generic) */
+    int64_t n[3];           /* INTERIOR extents; n[0] = x (contiguous); n[2] ignored for 2-D */
+    int64_t pitch_y;        /* elements per padded row; 0 = n[0]+2r */
+    int64_t pitch_z;        /* elements per padded plane; 0 = pitch_y*(n[1]+2r) */
+    const double *coef;     /* host: HEAT {centre, neighbour}; WAVE25 {c0..c4};
+                               GENERIC one value per coefficient id; POISSON19 unused */
+    int32_t n_coef;
+    int32_t n_taps;         /* GENERIC: number of taps */
+    const int32_t *tap_off; /* GENERIC: n_taps triples (dx,dy,dz), |d| <= radius */
+    const int32_t *tap_cid; /* GENERIC: coefficient id per tap, 0 <= id < n_coef */
+    double omega;           /* POISSON19 relaxation factor */
+    int32_t tile_x;         /* threads along x per block; 0 = let the plan decide */
+    int32_t tile_y;         /* rows per block tile; 0 = let the plan decide */
+    int32_t zblock;         /* z planes per block (saturated forms); 0 = let the plan decide */
+    int32_t reserved;
+} stencil_desc;
+
+/* Build a plan: validate d (host only, no device call before validation
+ * passes), choose variant and tile, allocate the plan's small buffers.
+ * On success *out is a new plan; on error *out = NULL. */
+stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out);
+
+/* Run `iterations` sweeps asynchronously on `stream`.
+ * fields (device pointers):
+ *   HEAT*, GENERIC, POISSON19: fields[0] = state (in/out), fields[1] = a
+ *     scratch grid of the same layout; the library first copies the halo of
+ *     fields[0] into fields[1] and ping-pongs; the result ends in fields[0].
+ *   WAVE25: fields[0] = u^{n-1}, fields[1] = u^n; each step overwrites the
+ *     interior of the older level in place, so after T steps the newest
+ *     level u^{n+T} is in fields[T % 2 == 1 ? 0 : 1] and the other holds
+ *     u^{n+T-1}.  Each buffer keeps its own halo.
+ * coef_arrays (device pointers): POISSON19: 12 F32 grids of the state's
+ *   layout in the order a0 a1 a2 a3 b0 b1 b2 c0 c1 c2 bnd wrk1;
+ *   WAVE25: {vsq} (F64 grid); others: NULL.
+ * Every pointer must be aligned to its element size.  iterations == 0 is a
+ * no-op.  The residual of the last sweep is kept for stencil_residual. */
+stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *const *coef_arrays,
+                           int32_t iterations, void *stream);
+
+/* Residual of the last sweep of the last run, FP64: sum over the interior of
+ * (new - old)^2 (POISSON19: sum of ss^2).  Reduces the per-block partials in
+ * a fixed order (bitwise reproducible), copies 8 bytes to the host and
+ * synchronizes `stream`.  E_STATE if no sweep has run on this plan. */
+stencil_status stencil_residual(stencil_plan_t p, double *host_out, void *stream);
+
+/* Chosen configuration of a plan (any output pointer may be NULL). */
+stencil_status stencil_plan_config(stencil_plan_t p, int32_t *variant, int32_t *tile_x, int32_t *tile_y,
+                                   int32_t *zblock);
+
+/* Sweep timing.  When enabled, stencil_run records HIP events on its stream
+ * around its sweep launches (after the halo copy, before any tail copy);
+ * stencil_profile_read waits for the last run's end event and returns its
+ * elapsed milliseconds and sweep count. */
+stencil_status stencil_profile_enable(stencil_plan_t p, int32_t enable);
+stencil_status stencil_profile_read(stencil_plan_t p, double *sweep_ms, int32_t *sweeps);
+
+/* Release a plan and its buffers (waits for nothing; the caller must not
+ * destroy a plan while its work is in flight).  NULL is accepted. */
+stencil_status stencil_destroy(stencil_plan_t p);
+
+/* Description of the last error on this thread; never NULL. */
+const char *stencil_last_error(void);
+
+/* Library version string, e.g. "0.1.0 gfx950". */
+const char *stencil_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STENCIL_H */

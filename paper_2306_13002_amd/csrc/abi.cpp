@@ -1,0 +1,387 @@
+// abi.cpp -- the C ABI of libstencil.so (declared in include/stencil.h).
+//
+// Validation happens on the host before any HIP call; a plan owns only its
+// residual partials, a one-double result slot, a pinned host double and two
+// timing events.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/stencil.h"
+#include "internal.hpp"
+#include "plan.hpp"
+
+using namespace stn;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+bool log_on() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = std::getenv("STENCIL_LOG");
+        v = (e && *e && std::strcmp(e, "0") != 0) ? 1 : 0;
+    }
+    return v == 1;
+}
+
+}  // namespace
+
+namespace stn {
+
+stencil_status fail(stencil_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    if (log_on()) std::fprintf(stderr, "[stencil] error %d: %s\n", (int)st, buf);
+    return st;
+}
+
+void logf(const char *fmt, ...) {
+    if (!log_on()) return;
+    va_list ap;
+    va_start(ap, fmt);
+    std::fprintf(stderr, "[stencil] ");
+    std::vfprintf(stderr, fmt, ap);
+    std::fprintf(stderr, "\n");
+    va_end(ap);
+}
+
+stencil_status hip_fail(hipError_t e, const char *what) {
+    return fail(STENCIL_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+const KindOps *ops_for(int kind) {
+    switch (kind) {
+    case STENCIL_HEAT2D5: return &heat2d5_ops;
+    case STENCIL_HEAT3D7: return &heat3d7_ops;
+    case STENCIL_POISSON19: return &poisson19_ops;
+    case STENCIL_WAVE25: return &wave25_ops;
+    default: return nullptr;
+    }
+}
+
+int elem_bytes(int dtype) { return dtype == STENCIL_F32 ? 4 : 8; }
+
+// Library defaults (used when a tile field is 0 and tuning is FIXED).
+Tile default_tile(int kind, int variant, const Geom &g) {
+    if (variant == V_PLAIN) return kind == STENCIL_HEAT2D5 ? Tile{64, 4, 1} : Tile{64, 4, 1};
+    switch (kind) {
+    case STENCIL_HEAT3D7: return Tile{64, 4, g.nz < 64 ? g.nz : 64};
+    case STENCIL_POISSON19: return Tile{64, 4, 16};
+    case STENCIL_WAVE25: return Tile{64, 8, 64};
+    default: return Tile{64, 4, 16};
+    }
+}
+
+// Validate the descriptor (host only).  Fills geometry on success.
+stencil_status validate_desc(const stencil_desc *d, Geom &g, int &rz) {
+    if (!d) return fail(STENCIL_E_INVAL, "descriptor is NULL");
+    if (d->struct_size != sizeof(stencil_desc))
+        return fail(STENCIL_E_INVAL, "struct_size %u != sizeof(stencil_desc) %zu", d->struct_size,
+                    sizeof(stencil_desc));
+    const int k = d->kind;
+    if (k < STENCIL_HEAT2D5 || k > STENCIL_GENERIC) return fail(STENCIL_E_INVAL, "unknown kind %d", k);
+    if (d->dtype != STENCIL_F32 && d->dtype != STENCIL_F64) return fail(STENCIL_E_INVAL, "unknown dtype %d", d->dtype);
+    if (d->variant < STENCIL_PLAIN || d->variant > STENCIL_AUTO)
+        return fail(STENCIL_E_INVAL, "unknown variant %d", d->variant);
+    if (d->tune < STENCIL_TUNE_FIXED || d->tune > STENCIL_TUNE_MODEL)
+        return fail(STENCIL_E_INVAL, "unknown tune mode %d", d->tune);
+    if (d->bc != STENCIL_BC_DIRICHLET && d->bc != STENCIL_BC_PERIODIC)
+        return fail(STENCIL_E_INVAL, "unknown boundary condition %d", d->bc);
+    const int want_ndim = (k == STENCIL_HEAT2D5) ? 2 : 3;
+    if (d->ndim != want_ndim) return fail(STENCIL_E_INVAL, "kind %d needs ndim %d, got %d", k, want_ndim, d->ndim);
+    int want_r = (k == STENCIL_WAVE25) ? 4 : 1;
+    if (k == STENCIL_GENERIC) {
+        if (d->radius < 1 || d->radius > 4) return fail(STENCIL_E_INVAL, "generic radius %d not in 1..4", d->radius);
+        want_r = d->radius;
+    }
+    if (d->radius != want_r) return fail(STENCIL_E_INVAL, "kind %d needs radius %d, got %d", k, want_r, d->radius);
+    const int nd = d->ndim;
+    for (int a = 0; a < nd; ++a)
+        if (d->n[a] < 1 || d->n[a] > (1 << 24))
+            return fail(STENCIL_E_INVAL, "interior extent n[%d] = %lld out of range [1, 2^24]", a, (long long)d->n[a]);
+    const int r = want_r;
+    const long long PX = d->n[0] + 2 * r, PY = d->n[1] + 2 * r, PZ = nd == 3 ? d->n[2] + 2 * r : 1;
+    const long long py = d->pitch_y ? d->pitch_y : PX;
+    const long long pz = nd == 3 ? (d->pitch_z ? d->pitch_z : py * PY) : py * PY;
+    if (py < PX) return fail(STENCIL_E_INVAL, "pitch_y %lld < padded row length %lld", py, PX);
+    if (nd == 3 && pz < py * PY) return fail(STENCIL_E_INVAL, "pitch_z %lld < pitch_y*padded rows %lld", pz, py * PY);
+    if ((double)pz * (double)PZ > 9.0e18) return fail(STENCIL_E_INVAL, "grid too large");
+    // dtype per kind
+    if ((k == STENCIL_HEAT2D5 || k == STENCIL_HEAT3D7 || k == STENCIL_WAVE25) && d->dtype != STENCIL_F64)
+        return fail(STENCIL_E_UNSUPPORTED, "kind %d is offered in F64 only", k);
+    if (k == STENCIL_POISSON19 && d->dtype != STENCIL_F32)
+        return fail(STENCIL_E_UNSUPPORTED, "POISSON19 is offered with F32 storage only");
+    // coefficients
+    if (k == STENCIL_HEAT2D5 || k == STENCIL_HEAT3D7) {
+        if (!d->coef || d->n_coef != 2) return fail(STENCIL_E_INVAL, "heat kinds need coef = {centre, neighbour}");
+    } else if (k == STENCIL_WAVE25) {
+        if (!d->coef || d->n_coef != 5) return fail(STENCIL_E_INVAL, "WAVE25 needs 5 coefficients");
+    } else if (k == STENCIL_POISSON19) {
+        if (!std::isfinite(d->omega)) return fail(STENCIL_E_INVAL, "omega must be finite");
+    } else {
+        if (!d->coef || d->n_coef < 1) return fail(STENCIL_E_INVAL, "GENERIC needs n_coef >= 1 coefficients");
+        if (d->n_taps < 1 || d->n_taps > 729 || !d->tap_off || !d->tap_cid)
+            return fail(STENCIL_E_INVAL, "GENERIC needs 1..729 taps with tap_off and tap_cid");
+        for (int t = 0; t < d->n_taps; ++t) {
+            for (int a = 0; a < 3; ++a)
+                if (d->tap_off[3 * t + a] < -r || d->tap_off[3 * t + a] > r)
+                    return fail(STENCIL_E_INVAL, "tap %d offset outside the radius", t);
+            if (d->tap_cid[t] < 0 || d->tap_cid[t] >= d->n_coef)
+                return fail(STENCIL_E_INVAL, "tap %d coefficient id %d out of range", t, d->tap_cid[t]);
+        }
+    }
+    if (d->coef)
+        for (int c = 0; c < d->n_coef; ++c)
+            if (!std::isfinite(d->coef[c])) return fail(STENCIL_E_INVAL, "coefficient %d is not finite", c);
+    if (d->bc == STENCIL_BC_PERIODIC && k != STENCIL_HEAT2D5 && k != STENCIL_HEAT3D7)
+        return fail(STENCIL_E_UNSUPPORTED, "periodic boundaries are offered for the heat kinds only");
+    if (d->tile_x < 0 || d->tile_y < 0 || d->zblock < 0) return fail(STENCIL_E_INVAL, "negative tile field");
+    g.nx = (int)d->n[0];
+    g.ny = (int)d->n[1];
+    g.nz = nd == 3 ? (int)d->n[2] : 1;
+    g.r = r;
+    g.py = py;
+    g.pz = pz;
+    rz = nd == 3 ? r : 0;
+    return STENCIL_OK;
+}
+
+long long span_elems(const stencil_plan_s *p) {
+    return (long long)(p->g.nz + 2 * p->rz - 1) * p->g.pz + (long long)(p->g.ny + 2 * p->g.r - 1) * p->g.py +
+           (p->g.nx + 2 * p->g.r);
+}
+
+stencil_status alloc_plan_buffers(stencil_plan_s *p) {
+    hipError_t e;
+    p->nblocks = p->ops->nblocks(p->variant, p->tile, p->g);
+    if ((e = hipMalloc(&p->d_part, sizeof(double) * (size_t)p->nblocks)) != hipSuccess)
+        return fail(STENCIL_E_NOMEM, "hipMalloc residual partials (%lld blocks): %s", p->nblocks, hipGetErrorString(e));
+    if ((e = hipMalloc(&p->d_result, sizeof(double))) != hipSuccess)
+        return fail(STENCIL_E_NOMEM, "hipMalloc result: %s", hipGetErrorString(e));
+    if ((e = hipHostMalloc(&p->h_result, sizeof(double), hipHostMallocDefault)) != hipSuccess)
+        return fail(STENCIL_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    if ((e = hipEventCreate(&p->ev0)) != hipSuccess || (e = hipEventCreate(&p->ev1)) != hipSuccess)
+        return hip_fail(e, "hipEventCreate");
+    return STENCIL_OK;
+}
+
+void free_plan(stencil_plan_s *p) {
+    if (!p) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (p->device >= 0) (void)hipSetDevice(p->device);
+    if (p->d_part) (void)hipFree(p->d_part);
+    if (p->d_result) (void)hipFree(p->d_result);
+    if (p->h_result) (void)hipHostFree(p->h_result);
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    if (cur >= 0) (void)hipSetDevice(cur);
+    delete p;
+}
+
+// Make the plan's device current for the lifetime of the guard.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = (prev == dev) || hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int now = -1;
+        if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+    }
+};
+
+stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
+    const KindOps *ops = p->ops;
+    const bool has_sat = ops->tile_ok(V_SATURATED, default_tile(p->kind, V_SATURATED, p->g));
+    int v = d->variant;
+    if (v == STENCIL_AUTO) v = has_sat ? V_SATURATED : V_PLAIN;
+    if (v == V_SATURATED && !has_sat)
+        return fail(STENCIL_E_UNSUPPORTED, "kind %d has no saturated form", p->kind);
+    Tile t = default_tile(p->kind, v, p->g);
+    if (d->tile_x) t.tx = d->tile_x;
+    if (d->tile_y) t.ty = d->tile_y;
+    if (d->zblock) t.tz = d->zblock;
+    if (!ops->tile_ok(v, t))
+        return fail(STENCIL_E_UNSUPPORTED, "tile (%d, %d, %d) is not offered for kind %d variant %d", t.tx, t.ty, t.tz,
+                    p->kind, v);
+    p->variant = v;
+    p->tile = t;
+    return STENCIL_OK;
+}
+
+}  // namespace stn
+
+extern "C" {
+
+stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out) {
+    if (!out) return fail(STENCIL_E_INVAL, "out is NULL");
+    *out = nullptr;
+    Geom g{};
+    int rz = 0;
+    stencil_status st = validate_desc(d, g, rz);
+    if (st != STENCIL_OK) return st;
+    if (d->kind == STENCIL_GENERIC) return fail(STENCIL_E_UNSUPPORTED, "GENERIC stencils are not built into this library yet");
+    if (d->tune != STENCIL_TUNE_FIXED)
+        return fail(STENCIL_E_UNSUPPORTED, "tune mode %d is not available in this build", d->tune);
+    // device
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) return fail(STENCIL_E_DEVICE, "no HIP device available");
+    stencil_plan_s *p = new (std::nothrow) stencil_plan_s();
+    if (!p) return fail(STENCIL_E_NOMEM, "host allocation failed");
+    p->kind = d->kind;
+    p->dtype = d->dtype;
+    p->bc = d->bc;
+    p->g = g;
+    p->rz = rz;
+    p->omega = d->omega;
+    p->ops = ops_for(d->kind);
+    for (int c = 0; c < 5; ++c) p->c[c] = (d->coef && c < d->n_coef) ? d->coef[c] : 0.0;
+    if ((e = hipGetDevice(&p->device)) != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDevice");
+    }
+    if ((st = choose_config(p, d)) != STENCIL_OK || (st = alloc_plan_buffers(p)) != STENCIL_OK) {
+        free_plan(p);
+        return st;
+    }
+    logf("plan kind=%d variant=%d tile=(%d,%d,%d) n=(%d,%d,%d) blocks=%lld", p->kind, p->variant, p->tile.tx,
+         p->tile.ty, p->tile.tz, g.nx, g.ny, g.nz, p->nblocks);
+    *out = p;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *const *coef_arrays, int32_t iterations,
+                           void *stream_) {
+    if (!p) return fail(STENCIL_E_INVAL, "plan is NULL");
+    if (!fields || !fields[0] || !fields[1]) return fail(STENCIL_E_INVAL, "fields[0] and fields[1] are required");
+    if (fields[0] == fields[1]) return fail(STENCIL_E_INVAL, "fields[0] and fields[1] must be distinct");
+    if (iterations < 0) return fail(STENCIL_E_INVAL, "iterations < 0");
+    const int eb = elem_bytes(p->dtype);
+    for (int f = 0; f < 2; ++f)
+        if ((uintptr_t)fields[f] % eb) return fail(STENCIL_E_INVAL, "fields[%d] is not %d-byte aligned", f, eb);
+    SweepArgs a{};
+    a.g = p->g;
+    for (int c = 0; c < 5; ++c) a.c[c] = p->c[c];
+    a.omega = p->omega;
+    if (p->kind == STENCIL_POISSON19) {
+        if (!coef_arrays) return fail(STENCIL_E_INVAL, "POISSON19 needs 12 coefficient arrays");
+        for (int c = 0; c < 12; ++c) {
+            if (!coef_arrays[c] || (uintptr_t)coef_arrays[c] % 4)
+                return fail(STENCIL_E_INVAL, "coefficient array %d is NULL or misaligned", c);
+            a.coefs[c] = coef_arrays[c];
+        }
+    } else if (p->kind == STENCIL_WAVE25) {
+        if (!coef_arrays || !coef_arrays[0] || (uintptr_t)coef_arrays[0] % 8)
+            return fail(STENCIL_E_INVAL, "WAVE25 needs coef_arrays = {vsq} (F64, aligned)");
+        a.coefs[0] = coef_arrays[0];
+    }
+    if (iterations == 0) return STENCIL_OK;
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return fail(STENCIL_E_DEVICE, "cannot make device %d current", p->device);
+    hipStream_t s = (hipStream_t)stream_;
+    hipError_t e;
+    p->has_resid = false;
+    const bool wave = p->kind == STENCIL_WAVE25;
+    if (!wave && p->bc == STENCIL_BC_DIRICHLET) {
+        if ((e = launch_halo_copy(fields[0], fields[1], eb, p->g, p->rz, s)) != hipSuccess)
+            return hip_fail(e, "halo copy launch");
+    }
+    if (p->profiling && (e = hipEventRecord(p->ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    void *src = fields[0], *dst = fields[1];
+    for (int t = 0; t < iterations; ++t) {
+        if (p->bc == STENCIL_BC_PERIODIC && (e = launch_periodic_fill(src, eb, p->g, p->rz, s)) != hipSuccess)
+            return hip_fail(e, "periodic fill launch");
+        a.src = src;
+        a.dst = dst;
+        a.part = (t == iterations - 1) ? p->d_part : nullptr;
+        if ((e = p->ops->launch(p->variant, p->tile, a, s)) != hipSuccess) return hip_fail(e, "sweep launch");
+        void *tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    if (p->profiling) {
+        if ((e = hipEventRecord(p->ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        p->prof_sweeps = iterations;
+        p->prof_valid = true;
+    }
+    if (!wave && (iterations & 1)) {
+        if ((e = launch_interior_copy(fields[1], fields[0], eb, p->g, p->rz, s)) != hipSuccess)
+            return hip_fail(e, "tail copy launch");
+    }
+    p->has_resid = true;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_residual(stencil_plan_t p, double *host_out, void *stream_) {
+    if (!p || !host_out) return fail(STENCIL_E_INVAL, "plan and host_out are required");
+    if (!p->has_resid) return fail(STENCIL_E_STATE, "no sweep has run on this plan");
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return fail(STENCIL_E_DEVICE, "cannot make device %d current", p->device);
+    hipStream_t s = (hipStream_t)stream_;
+    hipError_t e;
+    if ((e = launch_reduce_partials(p->d_part, p->nblocks, p->d_result, s)) != hipSuccess)
+        return hip_fail(e, "reduce launch");
+    if ((e = hipMemcpyAsync(p->h_result, p->d_result, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    *host_out = *p->h_result;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_plan_config(stencil_plan_t p, int32_t *variant, int32_t *tile_x, int32_t *tile_y,
+                                   int32_t *zblock) {
+    if (!p) return fail(STENCIL_E_INVAL, "plan is NULL");
+    if (variant) *variant = p->variant;
+    if (tile_x) *tile_x = p->tile.tx;
+    if (tile_y) *tile_y = p->tile.ty;
+    if (zblock) *zblock = p->tile.tz;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_profile_enable(stencil_plan_t p, int32_t enable) {
+    if (!p) return fail(STENCIL_E_INVAL, "plan is NULL");
+    p->profiling = enable != 0;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_profile_read(stencil_plan_t p, double *sweep_ms, int32_t *sweeps) {
+    if (!p || !sweep_ms) return fail(STENCIL_E_INVAL, "plan and sweep_ms are required");
+    if (!p->prof_valid) return fail(STENCIL_E_STATE, "no profiled run on this plan");
+    DeviceGuard guard(p->device);
+    hipError_t e;
+    if ((e = hipEventSynchronize(p->ev1)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, p->ev0, p->ev1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    *sweep_ms = ms;
+    if (sweeps) *sweeps = p->prof_sweeps;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_destroy(stencil_plan_t p) {
+    free_plan(p);
+    return STENCIL_OK;
+}
+
+const char *stencil_last_error(void) { return g_err.c_str(); }
+
+const char *stencil_version(void) { return "0.1.0 gfx950"; }
+
+}  // extern "C"

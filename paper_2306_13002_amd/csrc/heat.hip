@@ -1,0 +1,193 @@
+// heat.hip -- Jacobi heat sweeps: 2-D five-point and 3-D seven-point, FP64.
+//
+//   2-D:  dst = cc*u + cn*u(-x) + cn*u(+x) + cn*u(-y) + cn*u(+y)
+//   3-D:  ... + cn*u(-z) + cn*u(+z)
+//
+// PLAIN: the loop body as written, one thread per interior point, every
+// operand loaded from memory, products rounded and added left to right (the
+// library is compiled with -ffp-contract=off, so no FMA is formed).  This
+// is the paper's "original" code for its Jacobi class.
+//
+// SATURATED (3-D): the paper's rewrites applied by hand.  COMM/ASSOC regroup
+// the six neighbour products so the shared coefficient is applied once,
+// FMA1 fuses it with the centre term:  dst = fma(cn, (xm+xp)+(ym+yp)+(zm+zp), cc*u).
+// Loads: each block owns a TX x TY column tile and streams z; the centre
+// column lives in a three-deep register queue (each value loaded once), the
+// in-plane neighbours come from an LDS tile, and the next plane's loads are
+// all issued before the current plane is computed ("bulk load").
+#include "internal.hpp"
+
+namespace stn {
+namespace {
+
+constexpr int kMaxWaves = 16;  // blocks of at most 1024 threads
+
+__global__ void heat2d5_plain(const double *__restrict__ src, double *__restrict__ dst, Geom g, double cc,
+                              double cn, double *__restrict__ part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    double d2 = 0.0;
+    if (i < g.nx && j < g.ny) {
+        const long long q = (long long)(j + 1) * g.py + (i + 1);
+        const double u = src[q];
+        double v = cc * u;
+        v = v + cn * src[q - 1];
+        v = v + cn * src[q + 1];
+        v = v + cn * src[q - g.py];
+        v = v + cn * src[q + g.py];
+        dst[q] = v;
+        const double d = v - u;
+        d2 = d * d;
+    }
+    if (part) {
+        __shared__ double lds[kMaxWaves];
+        const double s = block_sum_f64(d2, lds);
+        if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = s;
+    }
+}
+
+__global__ void heat3d7_plain(const double *__restrict__ src, double *__restrict__ dst, Geom g, double cc,
+                              double cn, double *__restrict__ part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    double d2 = 0.0;
+    if (i < g.nx && j < g.ny && k < g.nz) {
+        const long long q = (long long)(k + 1) * g.pz + (long long)(j + 1) * g.py + (i + 1);
+        const double u = src[q];
+        double v = cc * u;
+        v = v + cn * src[q - 1];
+        v = v + cn * src[q + 1];
+        v = v + cn * src[q - g.py];
+        v = v + cn * src[q + g.py];
+        v = v + cn * src[q - g.pz];
+        v = v + cn * src[q + g.pz];
+        dst[q] = v;
+        const double d = v - u;
+        d2 = d * d;
+    }
+    if (part) {
+        __shared__ double lds[kMaxWaves];
+        const double s = block_sum_f64(d2, lds);
+        if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) part[block_linear_id()] = s;
+    }
+}
+
+// Saturated 3-D sweep.  Block (TX, TY) threads, one column each; grid
+// (ceil(nx/TX), ceil(ny/TY), ceil(nz/zb)).
+template <int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void heat3d7_sat(const double *__restrict__ src, double *__restrict__ dst,
+                                                      Geom g, double cc, double cn, int zb,
+                                                      double *__restrict__ part) {
+    constexpr int R = 1, W = TX + 2 * R, NT = TX * TY;
+    __shared__ double tile[2][(TY + 2 * R) * W];
+    __shared__ double red[kMaxWaves];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+    const int i = blockIdx.x * TX + tx, j = blockIdx.y * TY + ty;
+    const int xp = i + R, yp = j + R;
+    const int PX = g.nx + 2 * R, PY = g.ny + 2 * R, PZ = g.nz + 2 * R;
+    const bool in = i < g.nx && j < g.ny;
+    const bool ld = xp < PX && yp < PY;  // column inside the padded array (ring included)
+    const int k0 = blockIdx.z * zb, k1 = min(k0 + zb, g.nz);
+    const long long col = (long long)yp * g.py + xp;
+    const int me = (ty + R) * W + (tx + R);
+
+    HaloStager<double, TX, TY, R, false, NT> halo;
+    halo.init(tid, blockIdx.x * TX + R, blockIdx.y * TY + R, g.py, PX, PY);
+
+    // padded z of the plane being computed: zc = k + R
+    double prv = ld ? src[col + (long long)(k0)*g.pz] : 0.0;
+    double cur = ld ? src[col + (long long)(k0 + 1) * g.pz] : 0.0;
+    double nxt = ld ? src[col + (long long)(k0 + 2) * g.pz] : 0.0;
+    halo.load(src + (long long)(k0 + 1) * g.pz);
+    double acc = 0.0;
+
+    for (int k = k0; k < k1; ++k) {
+        const int zc = k + R;
+        const int b = (k - k0) & 1;
+        // stage plane zc: centre from the queue, ring from the stager
+        tile[b][me] = cur;
+        halo.store(tile[b]);
+        // bulk load: every global load of the next plane before this plane's math
+        const double nn = (ld && zc + 2 < PZ) ? src[col + (long long)(zc + 2) * g.pz] : 0.0;
+        if (k + 1 < k1) halo.load(src + (long long)(zc + 1) * g.pz);
+        __syncthreads();
+        if (in) {
+            const double *t = tile[b];
+            const double s = ((t[me - 1] + t[me + 1]) + (t[me - W] + t[me + W])) + (prv + nxt);
+            const double v = fma(cn, s, cc * cur);
+            dst[col + (long long)zc * g.pz] = v;
+            const double d = v - cur;
+            acc = fma(d, d, acc);
+        }
+        prv = cur;
+        cur = nxt;
+        nxt = nn;
+    }
+    if (part) {
+        const double s = block_sum_f64(acc, red);
+        if (tid == 0) part[block_linear_id()] = s;
+    }
+}
+
+// ----------------------------------------------------------------------------
+bool plain_tile_ok(Tile t) {
+    const long long n = (long long)t.tx * t.ty * t.tz;
+    return t.tx >= 1 && t.ty >= 1 && t.tz >= 1 && n % 64 == 0 && n <= 1024;
+}
+
+bool h2_tile_ok(int v, Tile t) { return v == V_PLAIN && plain_tile_ok(t) && t.tz == 1; }
+
+long long h2_nblocks(int, Tile t, const Geom &g) { return cdiv(g.nx, t.tx) * cdiv(g.ny, t.ty); }
+
+hipError_t h2_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
+    if (v != V_PLAIN) return hipErrorInvalidValue;
+    dim3 grid(cdiv(a.g.nx, t.tx), cdiv(a.g.ny, t.ty), 1), block(t.tx, t.ty, 1);
+    hipLaunchKernelGGL(heat2d5_plain, grid, block, 0, s, (const double *)a.src, (double *)a.dst, a.g, a.c[0],
+                       a.c[1], a.part);
+    return hipGetLastError();
+}
+
+// Saturated tiles offered: (TX, TY) with TX*TY a multiple of 64, <= 1024.
+#define HEAT3D7_SAT_TILES(X) X(32, 2) X(32, 4) X(32, 8) X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(128, 1) X(128, 2) \
+    X(128, 4) X(256, 1) X(256, 2)
+
+bool h3_tile_ok(int v, Tile t) {
+    if (v == V_PLAIN) return plain_tile_ok(t);
+    if (t.tz < 1) return false;
+#define X(a, b) if (t.tx == a && t.ty == b) return true;
+    HEAT3D7_SAT_TILES(X)
+#undef X
+    return false;
+}
+
+long long h3_nblocks(int v, Tile t, const Geom &g) {
+    return cdiv(g.nx, t.tx) * cdiv(g.ny, t.ty) * cdiv(g.nz, t.tz);
+}
+
+hipError_t h3_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
+    const double *src = (const double *)a.src;
+    double *dst = (double *)a.dst;
+    dim3 grid(cdiv(a.g.nx, t.tx), cdiv(a.g.ny, t.ty), cdiv(a.g.nz, t.tz));
+    if (v == V_PLAIN) {
+        hipLaunchKernelGGL(heat3d7_plain, grid, dim3(t.tx, t.ty, t.tz), 0, s, src, dst, a.g, a.c[0], a.c[1],
+                           a.part);
+        return hipGetLastError();
+    }
+#define X(A, B)                                                                                        \
+    if (t.tx == A && t.ty == B) {                                                                      \
+        hipLaunchKernelGGL((heat3d7_sat<A, B>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.c[0], a.c[1], \
+                           t.tz, a.part);                                                              \
+        return hipGetLastError();                                                                      \
+    }
+    HEAT3D7_SAT_TILES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+KindOps heat2d5_ops = {h2_tile_ok, h2_nblocks, h2_launch};
+KindOps heat3d7_ops = {h3_tile_ok, h3_nblocks, h3_launch};
+
+}  // namespace stn

@@ -1,0 +1,49 @@
+// internal.hpp -- host-side interface between the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace stn {
+
+enum Variant { V_PLAIN = 0, V_SATURATED = 1 };
+
+// Launch shape.  Plain forms: block = (tx, ty, tz) threads, one per point.
+// Saturated forms: tx threads along x, a tile of ty rows, zblock planes
+// streamed per block.
+struct Tile {
+    int tx, ty, tz;
+};
+
+// Arguments of one sweep launch.
+struct SweepArgs {
+    const void *src;          // Jacobi kinds: state read; WAVE25: u^n
+    void *dst;                // Jacobi kinds: state written; WAVE25: u^{n-1} in, u^{n+1} out
+    const void *coefs[12];    // POISSON19: a0 a1 a2 a3 b0 b1 b2 c0 c1 c2 bnd wrk1; WAVE25: vsq
+    Geom g;
+    double c[5];              // scalar coefficients (heat: cc, cn; wave: c0..c4)
+    double omega;             // POISSON19
+    double *part;             // residual partial per block, or nullptr
+    const int *taps;          // GENERIC: device tap table
+    const double *tap_coef;   // GENERIC: device coefficient table
+    int n_taps, n_coef;
+};
+
+struct KindOps {
+    bool (*tile_ok)(int variant, Tile t);
+    long long (*nblocks)(int variant, Tile t, const Geom &g);
+    hipError_t (*launch)(int variant, Tile t, const SweepArgs &a, hipStream_t s);
+};
+
+extern KindOps heat2d5_ops, heat3d7_ops, poisson19_ops, wave25_ops;
+
+// Support kernels (support.hip).
+hipError_t launch_halo_copy(const void *src, void *dst, int elem_bytes, const Geom &g, int rz, hipStream_t s);
+hipError_t launch_periodic_fill(void *buf, int elem_bytes, const Geom &g, int rz, hipStream_t s);
+hipError_t launch_interior_copy(const void *src, void *dst, int elem_bytes, const Geom &g, int rz, hipStream_t s);
+hipError_t launch_reduce_partials(const double *part, long long n, double *out, hipStream_t s);
+
+inline long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
+
+}  // namespace stn

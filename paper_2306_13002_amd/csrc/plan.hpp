@@ -1,0 +1,27 @@
+// plan.hpp -- the opaque plan object behind stencil_plan_t.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/stencil.h"
+#include "internal.hpp"
+
+struct stencil_plan_s {
+    int kind = 0, dtype = 0, bc = 0;
+    int variant = 0;            // resolved: stn::V_PLAIN or stn::V_SATURATED
+    stn::Tile tile{};           // resolved launch shape
+    stn::Geom g{};
+    int rz = 0;                 // z halo width (0 for 2-D)
+    double c[5] = {0, 0, 0, 0, 0};
+    double omega = 0;
+    const stn::KindOps *ops = nullptr;
+    int device = -1;
+    long long nblocks = 0;      // blocks of one sweep launch = residual partial count
+    double *d_part = nullptr;   // device: per-block residual partials of the last sweep
+    double *d_result = nullptr; // device: reduced residual
+    double *h_result = nullptr; // pinned host copy
+    bool has_resid = false;
+    bool profiling = false, prof_valid = false;
+    int prof_sweeps = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};

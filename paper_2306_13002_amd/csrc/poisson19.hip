@@ -1,0 +1,209 @@
+// poisson19.hip -- 19-point variable-coefficient pressure relaxation.
+//
+// F32 storage, FP64 arithmetic: every operand is widened on load and the new
+// p is rounded to F32 on store; the residual sum ss^2 is FP64.  (i,j,k) =
+// (x,y,z) and every coefficient array is read at the point itself:
+//
+//   s0 = a0*p(i+1,j,k) + a1*p(i,j+1,k) + a2*p(i,j,k+1)
+//      + b0*(p(i+1,j+1,k) - p(i+1,j-1,k) - p(i-1,j+1,k) + p(i-1,j-1,k))
+//      + b1*(p(i,j+1,k+1) - p(i,j-1,k+1) - p(i,j+1,k-1) + p(i,j-1,k-1))
+//      + b2*(p(i+1,j,k+1) - p(i-1,j,k+1) - p(i+1,j,k-1) + p(i-1,j,k-1))
+//      + c0*p(i-1,j,k) + c1*p(i,j-1,k) + c2*p(i,j,k-1) + wrk1
+//   ss = (s0*a3 - p)*bnd ;  p' = p + omega*ss ;  residual += ss^2
+//
+// This is the memory-bound halo-3D CFD loop-nest class of the paper's
+// benchmark tables (NPB BT/LU/SP, SPEC csp/bt): 12 coefficient streams, one
+// state stream read and one written, 56 algorithmic bytes per point.
+//
+// PLAIN: one thread per point, 19 + 12 loads, terms in the order above,
+// products rounded and added left to right (no contraction): bit-identical
+// to a plain FP64 loop nest that rounds stored p to F32.
+//
+// SATURATED: the cross terms are rewritten with COMM/ASSOC into differences
+// of differences, e.g. b1*(D(k+1) - D(k-1)) with D(k') = p(i,j+1,k') -
+// p(i,j-1,k') (a difference of two widened F32 values is exact in FP64),
+// and the whole s0 becomes one FMA chain (FMA1/FMA3).  Each block streams a
+// TX x TY column tile along z: the p planes k-1, k, k+1 sit in a four-deep
+// LDS ring (one barrier per plane), and every global load of the next plane
+// -- its p tile and the 12 coefficients -- is issued before the current
+// plane is computed ("bulk load"), so each wave keeps ~13 loads in flight.
+#include "internal.hpp"
+
+namespace stn {
+namespace {
+
+constexpr int kMaxWaves = 16;
+
+// a0 a1 a2 a3 b0 b1 b2 c0 c1 c2 bnd wrk1
+enum { A0, A1, A2, A3, B0, B1, B2, C0, C1, C2, BND, WRK1 };
+struct P19Coef {
+    const float *f[12];
+};
+
+P19Coef pack(const SweepArgs &a) {
+    P19Coef c;
+    for (int i = 0; i < 12; ++i) c.f[i] = (const float *)a.coefs[i];
+    return c;
+}
+
+__global__ void poisson19_plain(const float *__restrict__ p, float *__restrict__ pn, P19Coef c, Geom g,
+                                double omega, double *__restrict__ part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    double d2 = 0.0;
+    if (i < g.nx && j < g.ny && k < g.nz) {
+        const long long q = (long long)(k + 1) * g.pz + (long long)(j + 1) * g.py + (i + 1);
+        const long long Y = g.py, Z = g.pz;
+#define P(dx, dy, dz) ((double)p[q + (dx) + (dy)*Y + (dz)*Z])
+        double s0 = (double)c.f[A0][q] * P(1, 0, 0);
+        s0 = s0 + (double)c.f[A1][q] * P(0, 1, 0);
+        s0 = s0 + (double)c.f[A2][q] * P(0, 0, 1);
+        s0 = s0 + (double)c.f[B0][q] * (((P(1, 1, 0) - P(1, -1, 0)) - P(-1, 1, 0)) + P(-1, -1, 0));
+        s0 = s0 + (double)c.f[B1][q] * (((P(0, 1, 1) - P(0, -1, 1)) - P(0, 1, -1)) + P(0, -1, -1));
+        s0 = s0 + (double)c.f[B2][q] * (((P(1, 0, 1) - P(-1, 0, 1)) - P(1, 0, -1)) + P(-1, 0, -1));
+        s0 = s0 + (double)c.f[C0][q] * P(-1, 0, 0);
+        s0 = s0 + (double)c.f[C1][q] * P(0, -1, 0);
+        s0 = s0 + (double)c.f[C2][q] * P(0, 0, -1);
+        s0 = s0 + (double)c.f[WRK1][q];
+        const double ss = (s0 * (double)c.f[A3][q] - P(0, 0, 0)) * (double)c.f[BND][q];
+        pn[q] = (float)(P(0, 0, 0) + omega * ss);
+#undef P
+        d2 = ss * ss;
+    }
+    if (part) {
+        __shared__ double lds[kMaxWaves];
+        const double s = block_sum_f64(d2, lds);
+        if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) part[block_linear_id()] = s;
+    }
+}
+
+template <int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void poisson19_sat(const float *__restrict__ p, float *__restrict__ pn,
+                                                        P19Coef c, Geom g, double omega, int zb,
+                                                        double *__restrict__ part) {
+    constexpr int R = 1, W = TX + 2 * R, NT = TX * TY, PLANE = (TY + 2 * R) * W;
+    __shared__ float ring[4][PLANE];
+    __shared__ double red[kMaxWaves];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+    const int i = blockIdx.x * TX + tx, j = blockIdx.y * TY + ty;
+    const int xp = i + R, yp = j + R;
+    const int PX = g.nx + 2 * R, PY = g.ny + 2 * R;
+    const bool in = i < g.nx && j < g.ny;
+    const bool ld = xp < PX && yp < PY;
+    const int k0 = blockIdx.z * zb, k1 = min(k0 + zb, g.nz);
+    const long long col = (long long)yp * g.py + xp;
+    const int me = (ty + R) * W + (tx + R);
+
+    HaloStager<float, TX, TY, R, true, NT> halo;
+    halo.init(tid, blockIdx.x * TX + R, blockIdx.y * TY + R, g.py, PX, PY);
+
+    // prologue: planes zc0-1 and zc0 (zc = k + 1) into the ring
+    for (int z = k0; z <= k0 + 1; ++z) {
+        const float *pl = p + (long long)z * g.pz;
+        ring[z & 3][me] = ld ? pl[col] : 0.0f;
+        halo.load(pl);
+        halo.store(ring[z & 3]);
+    }
+    // registers for the plane after: p(zc+1) tile and coefficients at zc
+    float ctr = ld ? p[col + (long long)(k0 + 2) * g.pz] : 0.0f;
+    halo.load(p + (long long)(k0 + 2) * g.pz);
+    float cf[12];
+    {
+        const long long q = col + (long long)(k0 + 1) * g.pz;
+#pragma unroll
+        for (int s = 0; s < 12; ++s) cf[s] = in ? c.f[s][q] : 0.0f;
+    }
+    double acc = 0.0;
+
+    for (int k = k0; k < k1; ++k) {
+        const int zc = k + 1;
+        // stage plane zc+1
+        ring[(zc + 1) & 3][me] = ctr;
+        halo.store(ring[(zc + 1) & 3]);
+        // keep this plane's coefficients, then bulk-issue every load of the next plane
+        float cc[12];
+#pragma unroll
+        for (int s = 0; s < 12; ++s) cc[s] = cf[s];
+        if (k + 1 < k1) {
+            const long long qn = col + (long long)(zc + 1) * g.pz;
+#pragma unroll
+            for (int s = 0; s < 12; ++s) cf[s] = in ? c.f[s][qn] : 0.0f;
+            const float *pl = p + (long long)(zc + 2) * g.pz;
+            ctr = ld ? pl[col] : 0.0f;
+            halo.load(pl);
+        }
+        __syncthreads();
+        if (in) {
+            const float *m = ring[(zc - 1) & 3], *o = ring[zc & 3], *u = ring[(zc + 1) & 3];
+            const double pc = o[me];
+            const double pE = o[me + 1], pW = o[me - 1], pN = o[me + W], pS = o[me - W];
+            const double B0v = ((double)o[me + W + 1] - (double)o[me - W + 1]) -
+                              ((double)o[me + W - 1] - (double)o[me - W - 1]);
+            const double B1v = ((double)u[me + W] - (double)u[me - W]) - ((double)m[me + W] - (double)m[me - W]);
+            const double B2v = ((double)u[me + 1] - (double)u[me - 1]) - ((double)m[me + 1] - (double)m[me - 1]);
+            const double pU = u[me], pD = m[me];
+            double s0 = fma((double)cc[B0], B0v, (double)cc[WRK1]);
+            s0 = fma((double)cc[B1], B1v, s0);
+            s0 = fma((double)cc[B2], B2v, s0);
+            s0 = fma((double)cc[A0], pE, s0);
+            s0 = fma((double)cc[C0], pW, s0);
+            s0 = fma((double)cc[A1], pN, s0);
+            s0 = fma((double)cc[C1], pS, s0);
+            s0 = fma((double)cc[A2], pU, s0);
+            s0 = fma((double)cc[C2], pD, s0);
+            const double ss = fma(s0, (double)cc[A3], -pc) * (double)cc[BND];
+            pn[col + (long long)zc * g.pz] = (float)fma(omega, ss, pc);
+            acc = fma(ss, ss, acc);
+        }
+    }
+    if (part) {
+        const double s = block_sum_f64(acc, red);
+        if (tid == 0) part[block_linear_id()] = s;
+    }
+}
+
+bool plain_tile_ok(Tile t) {
+    const long long n = (long long)t.tx * t.ty * t.tz;
+    return t.tx >= 1 && t.ty >= 1 && t.tz >= 1 && n % 64 == 0 && n <= 1024;
+}
+
+#define P19_SAT_TILES(X) X(32, 2) X(32, 4) X(32, 8) X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(128, 1) X(128, 2) \
+    X(128, 4) X(256, 1)
+
+bool p19_tile_ok(int v, Tile t) {
+    if (v == V_PLAIN) return plain_tile_ok(t);
+    if (t.tz < 1) return false;
+#define X(a, b) if (t.tx == a && t.ty == b) return true;
+    P19_SAT_TILES(X)
+#undef X
+    return false;
+}
+
+long long p19_nblocks(int, Tile t, const Geom &g) { return cdiv(g.nx, t.tx) * cdiv(g.ny, t.ty) * cdiv(g.nz, t.tz); }
+
+hipError_t p19_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
+    const float *src = (const float *)a.src;
+    float *dst = (float *)a.dst;
+    const P19Coef c = pack(a);
+    dim3 grid(cdiv(a.g.nx, t.tx), cdiv(a.g.ny, t.ty), cdiv(a.g.nz, t.tz));
+    if (v == V_PLAIN) {
+        hipLaunchKernelGGL(poisson19_plain, grid, dim3(t.tx, t.ty, t.tz), 0, s, src, dst, c, a.g, a.omega, a.part);
+        return hipGetLastError();
+    }
+#define X(A, B)                                                                                          \
+    if (t.tx == A && t.ty == B) {                                                                        \
+        hipLaunchKernelGGL((poisson19_sat<A, B>), grid, dim3(A, B, 1), 0, s, src, dst, c, a.g, a.omega, t.tz, \
+                           a.part);                                                                      \
+        return hipGetLastError();                                                                        \
+    }
+    P19_SAT_TILES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+KindOps poisson19_ops = {p19_tile_ok, p19_nblocks, p19_launch};
+
+}  // namespace stn

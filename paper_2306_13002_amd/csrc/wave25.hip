@@ -1,0 +1,227 @@
+// wave25.hip -- radius-4 25-point star, second order in time (leapfrog), FP64.
+//
+//   L(u)   = sum over axes x, y, z of [c0*u + sum_{q=1..4} c_q*(u(+q) + u(-q))]
+//   u_next = 2u - u_prev + vsq*L(u)
+//
+// The newer level u^n is read-only; u_next overwrites u_prev in place (a
+// point's update reads u_prev only at that point, so this is race-free).
+// 32 algorithmic bytes per point: read u^n, u^{n-1}, vsq, write u^{n+1}.
+//
+// PLAIN: one thread per point, 27 products in one left-to-right chain (axis
+// x, then y, then z; per axis c0*u, then q = 1..4 with +q before -q), no
+// contraction -- the loop body as written.
+//
+// SATURATED: the paper's rewrites by hand.  Constant folding merges the three
+// centre products into (3*c0)*u; COMM/ASSOC group the six taps at distance q
+// so each shared coefficient multiplies once; FMA1 chains the four radii and
+// the time update:  L = fma(c4,S4, fma(c3,S3, fma(c2,S2, fma(c1,S1, (3c0)*u)))),
+// u_next = fma(vsq, L, 2u - u_prev).  Loads: a block owns a TX x TY column
+// tile (BY thread rows, RY rows per thread) and streams z; each column keeps
+// the nine planes z-4..z+4 in a register queue (one global load per point),
+// the in-plane +-4 neighbours come from an LDS tile with a 4-cell ring, and
+// every load of the next plane (queue head, ring, u_prev, vsq) is issued
+// before the current plane is computed ("bulk load").
+#include "internal.hpp"
+
+namespace stn {
+namespace {
+
+constexpr int kMaxWaves = 16;
+
+struct W25C {
+    double c0, c1, c2, c3, c4, c0x3;
+};
+
+__global__ void wave25_plain(const double *__restrict__ cur, double *__restrict__ pn, const double *__restrict__ vsq,
+                             Geom g, W25C c, double *__restrict__ part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    double d2 = 0.0;
+    if (i < g.nx && j < g.ny && k < g.nz) {
+        const long long q = (long long)(k + 4) * g.pz + (long long)(j + 4) * g.py + (i + 4);
+        const long long X = 1, Y = g.py, Z = g.pz;
+        const double u = cur[q];
+        double L = c.c0 * u;
+        L = L + c.c1 * cur[q + X];
+        L = L + c.c1 * cur[q - X];
+        L = L + c.c2 * cur[q + 2 * X];
+        L = L + c.c2 * cur[q - 2 * X];
+        L = L + c.c3 * cur[q + 3 * X];
+        L = L + c.c3 * cur[q - 3 * X];
+        L = L + c.c4 * cur[q + 4 * X];
+        L = L + c.c4 * cur[q - 4 * X];
+        L = L + c.c0 * u;
+        L = L + c.c1 * cur[q + Y];
+        L = L + c.c1 * cur[q - Y];
+        L = L + c.c2 * cur[q + 2 * Y];
+        L = L + c.c2 * cur[q - 2 * Y];
+        L = L + c.c3 * cur[q + 3 * Y];
+        L = L + c.c3 * cur[q - 3 * Y];
+        L = L + c.c4 * cur[q + 4 * Y];
+        L = L + c.c4 * cur[q - 4 * Y];
+        L = L + c.c0 * u;
+        L = L + c.c1 * cur[q + Z];
+        L = L + c.c1 * cur[q - Z];
+        L = L + c.c2 * cur[q + 2 * Z];
+        L = L + c.c2 * cur[q - 2 * Z];
+        L = L + c.c3 * cur[q + 3 * Z];
+        L = L + c.c3 * cur[q - 3 * Z];
+        L = L + c.c4 * cur[q + 4 * Z];
+        L = L + c.c4 * cur[q - 4 * Z];
+        const double nv = (2.0 * u - pn[q]) + vsq[q] * L;
+        pn[q] = nv;
+        const double d = nv - u;
+        d2 = d * d;
+    }
+    if (part) {
+        __shared__ double lds[kMaxWaves];
+        const double s = block_sum_f64(d2, lds);
+        if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) part[block_linear_id()] = s;
+    }
+}
+
+template <int TX, int BY, int RY>
+__global__ __launch_bounds__(TX *BY) void wave25_sat(const double *__restrict__ cur, double *__restrict__ pn,
+                                                     const double *__restrict__ vsq, Geom g, W25C c, int zb,
+                                                     double *__restrict__ part) {
+    constexpr int R = 4, TY = BY * RY, W = TX + 2 * R, NT = TX * BY, PLANE = (TY + 2 * R) * W;
+    __shared__ double tile[2][PLANE];
+    __shared__ double red[kMaxWaves];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+    const int i = blockIdx.x * TX + tx, jb = blockIdx.y * TY + ty * RY;
+    const int xp = i + R;
+    const int PX = g.nx + 2 * R, PY = g.ny + 2 * R, PZ = g.nz + 2 * R;
+    const int k0 = blockIdx.z * zb, k1 = min(k0 + zb, g.nz);
+
+    bool in[RY], ld[RY];
+    long long col[RY];
+    int me[RY];
+#pragma unroll
+    for (int m = 0; m < RY; ++m) {
+        const int yp = jb + m + R;
+        in[m] = i < g.nx && jb + m < g.ny;
+        ld[m] = xp < PX && yp < PY;
+        col[m] = (long long)yp * g.py + xp;
+        me[m] = (ty * RY + m + R) * W + (tx + R);
+    }
+    HaloStager<double, TX, TY, R, false, NT> halo;
+    halo.init(tid, blockIdx.x * TX + R, blockIdx.y * TY + R, g.py, PX, PY);
+
+    // q[m][s] = u^n at padded z = zc - 4 + s, zc = k + 4 the plane computed
+    double q[RY][9], up[RY], vv[RY];
+#pragma unroll
+    for (int m = 0; m < RY; ++m) {
+#pragma unroll
+        for (int s = 0; s < 9; ++s) q[m][s] = ld[m] ? cur[col[m] + (long long)(k0 + s) * g.pz] : 0.0;
+        const long long o = col[m] + (long long)(k0 + R) * g.pz;
+        up[m] = in[m] ? pn[o] : 0.0;
+        vv[m] = in[m] ? vsq[o] : 0.0;
+    }
+    halo.load(cur + (long long)(k0 + R) * g.pz);
+    double acc = 0.0;
+
+    for (int k = k0; k < k1; ++k) {
+        const int zc = k + R, b = (k - k0) & 1;
+        double *t = tile[b];
+#pragma unroll
+        for (int m = 0; m < RY; ++m) t[me[m]] = q[m][4];
+        halo.store(t);
+        double upc[RY], vvc[RY], qn[RY];
+#pragma unroll
+        for (int m = 0; m < RY; ++m) {
+            upc[m] = up[m];
+            vvc[m] = vv[m];
+            qn[m] = 0.0;
+        }
+        if (k + 1 < k1) {  // bulk load of plane zc+1 (queue head zc+5)
+#pragma unroll
+            for (int m = 0; m < RY; ++m) qn[m] = (ld[m] && zc + 5 < PZ) ? cur[col[m] + (long long)(zc + 5) * g.pz] : 0.0;
+            halo.load(cur + (long long)(zc + 1) * g.pz);
+#pragma unroll
+            for (int m = 0; m < RY; ++m) {
+                const long long o = col[m] + (long long)(zc + 1) * g.pz;
+                up[m] = in[m] ? pn[o] : 0.0;
+                vv[m] = in[m] ? vsq[o] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < RY; ++m) {
+            if (in[m]) {
+                const int e = me[m];
+                const double u = q[m][4];
+                const double s1 = ((t[e - 1] + t[e + 1]) + (t[e - W] + t[e + W])) + (q[m][3] + q[m][5]);
+                const double s2 = ((t[e - 2] + t[e + 2]) + (t[e - 2 * W] + t[e + 2 * W])) + (q[m][2] + q[m][6]);
+                const double s3 = ((t[e - 3] + t[e + 3]) + (t[e - 3 * W] + t[e + 3 * W])) + (q[m][1] + q[m][7]);
+                const double s4 = ((t[e - 4] + t[e + 4]) + (t[e - 4 * W] + t[e + 4 * W])) + (q[m][0] + q[m][8]);
+                double L = c.c0x3 * u;
+                L = fma(c.c1, s1, L);
+                L = fma(c.c2, s2, L);
+                L = fma(c.c3, s3, L);
+                L = fma(c.c4, s4, L);
+                const double nv = fma(vvc[m], L, 2.0 * u - upc[m]);
+                pn[col[m] + (long long)zc * g.pz] = nv;
+                const double d = nv - u;
+                acc = fma(d, d, acc);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < RY; ++m) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) q[m][s] = q[m][s + 1];
+            q[m][8] = qn[m];
+        }
+    }
+    if (part) {
+        const double s = block_sum_f64(acc, red);
+        if (tid == 0) part[block_linear_id()] = s;
+    }
+}
+
+bool plain_tile_ok(Tile t) {
+    const long long n = (long long)t.tx * t.ty * t.tz;
+    return t.tx >= 1 && t.ty >= 1 && t.tz >= 1 && n % 64 == 0 && n <= 1024;
+}
+
+// Saturated tiles: (TX, tile rows) -> (TX, BY thread rows, RY rows per thread)
+#define W25_SAT_TILES(X) X(64, 4, 4, 1) X(64, 8, 4, 2) X(64, 16, 4, 4) X(64, 8, 8, 1) X(64, 16, 8, 2) \
+    X(32, 8, 8, 1) X(32, 16, 8, 2) X(128, 4, 4, 1) X(128, 8, 4, 2) X(128, 8, 8, 1) X(256, 4, 4, 1)
+
+bool w25_tile_ok(int v, Tile t) {
+    if (v == V_PLAIN) return plain_tile_ok(t);
+    if (t.tz < 1) return false;
+#define X(A_, TY_, BY_, RY_) if (t.tx == A_ && t.ty == TY_) return true;
+    W25_SAT_TILES(X)
+#undef X
+    return false;
+}
+
+long long w25_nblocks(int, Tile t, const Geom &g) { return cdiv(g.nx, t.tx) * cdiv(g.ny, t.ty) * cdiv(g.nz, t.tz); }
+
+hipError_t w25_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
+    const double *cur = (const double *)a.src;
+    double *pn = (double *)a.dst;
+    const double *vsq = (const double *)a.coefs[0];
+    W25C c{a.c[0], a.c[1], a.c[2], a.c[3], a.c[4], 3.0 * a.c[0]};
+    dim3 grid(cdiv(a.g.nx, t.tx), cdiv(a.g.ny, t.ty), cdiv(a.g.nz, t.tz));
+    if (v == V_PLAIN) {
+        hipLaunchKernelGGL(wave25_plain, grid, dim3(t.tx, t.ty, t.tz), 0, s, cur, pn, vsq, a.g, c, a.part);
+        return hipGetLastError();
+    }
+#define X(A, TY, BY, RY)                                                                                   \
+    if (t.tx == A && t.ty == TY) {                                                                         \
+        hipLaunchKernelGGL((wave25_sat<A, BY, RY>), grid, dim3(A, BY, 1), 0, s, cur, pn, vsq, a.g, c, t.tz, \
+                           a.part);                                                                        \
+        return hipGetLastError();                                                                          \
+    }
+    W25_SAT_TILES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+KindOps wave25_ops = {w25_tile_ok, w25_nblocks, w25_launch};
+
+}  // namespace stn

@@ -1,0 +1,245 @@
+"""Python binding of libstencil.so (the C ABI in include/stencil.h).
+
+Argument marshalling only: descriptors are packed into the C struct, torch
+tensors are checked (device, dtype, layout, size) and passed as raw device
+pointers, and every sweep runs in the library's HIP kernels.  There is no
+fallback: if libstencil.so is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstencil.so")
+
+OK, E_INVAL, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_STATE = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {OK: "OK", E_INVAL: "E_INVAL", E_UNSUPPORTED: "E_UNSUPPORTED", E_NOMEM: "E_NOMEM",
+                E_DEVICE: "E_DEVICE", E_STATE: "E_STATE"}
+KINDS = {"heat2d5": 1, "heat3d7": 2, "poisson19": 3, "wave25": 4, "generic": 5}
+DTYPES = {"f32": 1, "f64": 2}
+VARIANTS = {"plain": 0, "saturated": 1, "auto": 2}
+VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
+TUNES = {"fixed": 0, "exhaustive": 1, "model": 2}
+BCS = {"dirichlet": 0, "periodic": 1}
+RADIUS = {"heat2d5": 1, "heat3d7": 1, "poisson19": 1, "wave25": 4}
+DEFAULT_DTYPE = {"heat2d5": "f64", "heat3d7": "f64", "poisson19": "f32", "wave25": "f64", "generic": "f64"}
+
+
+class StencilDesc(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("kind", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("variant", ctypes.c_int32), ("tune", ctypes.c_int32), ("bc", ctypes.c_int32),
+        ("ndim", ctypes.c_int32), ("radius", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+        ("pitch_y", ctypes.c_int64), ("pitch_z", ctypes.c_int64),
+        ("coef", ctypes.POINTER(ctypes.c_double)), ("n_coef", ctypes.c_int32),
+        ("n_taps", ctypes.c_int32), ("tap_off", ctypes.POINTER(ctypes.c_int32)),
+        ("tap_cid", ctypes.POINTER(ctypes.c_int32)), ("omega", ctypes.c_double),
+        ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("zblock", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class StencilError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libstencil.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                               "python -m paper_2306_13002_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
+        L.stencil_plan.argtypes = [ctypes.POINTER(StencilDesc), ctypes.POINTER(vp)]
+        L.stencil_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
+        L.stencil_residual.argtypes = [vp, dp, vp]
+        L.stencil_plan_config.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
+        L.stencil_profile_enable.argtypes = [vp, i32]
+        L.stencil_profile_read.argtypes = [vp, dp, ctypes.POINTER(i32)]
+        L.stencil_destroy.argtypes = [vp]
+        for f in (L.stencil_plan, L.stencil_run, L.stencil_residual, L.stencil_plan_config,
+                  L.stencil_profile_enable, L.stencil_profile_read, L.stencil_destroy):
+            f.restype = ctypes.c_int
+        L.stencil_last_error.restype = ctypes.c_char_p
+        L.stencil_last_error.argtypes = []
+        L.stencil_version.restype = ctypes.c_char_p
+        L.stencil_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().stencil_last_error().decode()
+
+
+def _check(st: int):
+    if st != OK:
+        raise StencilError(st, last_error())
+
+
+def make_desc(kind: str, n: Sequence[int], dtype: Optional[str] = None, variant: str = "auto",
+              tune: str = "fixed", bc: str = "dirichlet", coef: Optional[Sequence[float]] = None,
+              taps: Optional[Sequence[Sequence[int]]] = None, cids: Optional[Sequence[int]] = None,
+              radius: Optional[int] = None, omega: float = 0.8, tile: Sequence[int] = (0, 0, 0),
+              pitch: Sequence[int] = (0, 0)):
+    """Pack a stencil_desc.  Returns (desc, keepalive) -- keep the second
+    object alive until stencil_plan has copied the host arrays."""
+    d = StencilDesc()
+    d.struct_size = ctypes.sizeof(StencilDesc)
+    d.kind = KINDS[kind]
+    d.dtype = DTYPES[dtype or DEFAULT_DTYPE[kind]]
+    d.variant = VARIANTS[variant]
+    d.tune = TUNES[tune]
+    d.bc = BCS[bc]
+    d.ndim = 2 if kind == "heat2d5" else 3
+    d.radius = int(radius if radius is not None else RADIUS.get(kind, 1))
+    nn = list(n) + [1] * (3 - len(n))
+    for a in range(3):
+        d.n[a] = int(nn[a])
+    d.pitch_y, d.pitch_z = int(pitch[0]), int(pitch[1])
+    keep = []
+    if coef is not None:
+        ca = (ctypes.c_double * len(coef))(*[float(c) for c in coef])
+        keep.append(ca)
+        d.coef = ctypes.cast(ca, ctypes.POINTER(ctypes.c_double))
+        d.n_coef = len(coef)
+    if taps is not None:
+        flat = [int(v) for t in taps for v in t]
+        ta = (ctypes.c_int32 * len(flat))(*flat)
+        ci = (ctypes.c_int32 * len(cids))(*[int(c) for c in cids])
+        keep += [ta, ci]
+        d.tap_off = ctypes.cast(ta, ctypes.POINTER(ctypes.c_int32))
+        d.tap_cid = ctypes.cast(ci, ctypes.POINTER(ctypes.c_int32))
+        d.n_taps = len(taps)
+    d.omega = float(omega)
+    d.tile_x, d.tile_y, d.zblock = (int(v) for v in tile)
+    return d, keep
+
+
+def plan_status(desc: StencilDesc) -> tuple[int, Optional[int]]:
+    """Call stencil_plan; returns (status, handle or None) without raising."""
+    h = ctypes.c_void_p()
+    st = lib().stencil_plan(ctypes.byref(desc), ctypes.byref(h))
+    return st, (h.value if st == OK else None)
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Plan:
+    """A built plan.  Grids are padded torch tensors (see include/stencil.h)."""
+
+    def __init__(self, kind: str, n: Sequence[int], **kw):
+        self.kind = kind
+        self.n = tuple(int(v) for v in n)
+        self.dtype = kw.get("dtype") or DEFAULT_DTYPE[kind]
+        self.radius = int(kw.get("radius") if kw.get("radius") is not None else RADIUS.get(kind, 1))
+        self.pitch = tuple(kw.get("pitch", (0, 0)))
+        desc, keep = make_desc(kind, n, **kw)
+        h = ctypes.c_void_p()
+        _check(lib().stencil_plan(ctypes.byref(desc), ctypes.byref(h)))
+        del keep
+        self._h = h
+
+    # layout --------------------------------------------------------------
+    def padded_shape(self):
+        r = self.radius
+        if self.kind == "heat2d5":
+            return (self.n[1] + 2 * r, self.n[0] + 2 * r)
+        return (self.n[2] + 2 * r, self.n[1] + 2 * r, self.n[0] + 2 * r)
+
+    def _span(self):
+        r = self.radius
+        PX, PY = self.n[0] + 2 * r, self.n[1] + 2 * r
+        py = self.pitch[0] or PX
+        if self.kind == "heat2d5":
+            return (PY - 1) * py + PX
+        PZ = self.n[2] + 2 * r
+        pz = self.pitch[1] or py * PY
+        return (PZ - 1) * pz + (PY - 1) * py + PX
+
+    def _check_tensor(self, t, dtype_name: str, what: str):
+        import torch
+        want = torch.float32 if dtype_name == "f32" else torch.float64
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{what} must be a torch tensor")
+        if t.device.type != "cuda":
+            raise ValueError(f"{what} must be a device (cuda) tensor")
+        if t.dtype != want:
+            raise TypeError(f"{what} must be {want}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous (use pitch= for padded rows)")
+        if t.numel() < self._span():
+            raise ValueError(f"{what} holds {t.numel()} elements, the padded grid spans {self._span()}")
+        if self.pitch == (0, 0) and tuple(t.shape) != self.padded_shape() and t.dim() != 1:
+            raise ValueError(f"{what} shape {tuple(t.shape)} != padded shape {self.padded_shape()}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    # calls ---------------------------------------------------------------
+    def run(self, fields, coef_arrays=None, iterations: int = 1, stream=None):
+        """Run `iterations` sweeps (asynchronous on `stream`, default: torch's
+        current stream).  For wave25, returns (older, newer) tensors."""
+        if len(fields) != 2:
+            raise ValueError("two field tensors are required")
+        fp = (ctypes.c_void_p * 2)(*[self._check_tensor(f, self.dtype, f"fields[{i}]") for i, f in enumerate(fields)])
+        cp = None
+        if self.kind == "poisson19":
+            if coef_arrays is None or len(coef_arrays) != 12:
+                raise ValueError("poisson19 needs 12 coefficient tensors")
+            cp = (ctypes.c_void_p * 12)(*[self._check_tensor(c, "f32", f"coef[{i}]") for i, c in enumerate(coef_arrays)])
+        elif self.kind == "wave25":
+            if coef_arrays is None or len(coef_arrays) != 1:
+                raise ValueError("wave25 needs coef_arrays = [vsq]")
+            cp = (ctypes.c_void_p * 1)(self._check_tensor(coef_arrays[0], "f64", "vsq"))
+        _check(lib().stencil_run(self._h, fp, cp, int(iterations), ctypes.c_void_p(_stream_handle(stream))))
+        if self.kind == "wave25":
+            return (fields[1], fields[0]) if iterations % 2 == 1 else (fields[0], fields[1])
+        return fields[0]
+
+    def residual(self, stream=None) -> float:
+        out = ctypes.c_double()
+        _check(lib().stencil_residual(self._h, ctypes.byref(out), ctypes.c_void_p(_stream_handle(stream))))
+        return out.value
+
+    def config(self) -> dict:
+        v, tx, ty, zb = (ctypes.c_int32() for _ in range(4))
+        _check(lib().stencil_plan_config(self._h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(zb)))
+        return {"variant": VARIANT_NAMES[v.value], "tile": (tx.value, ty.value, zb.value)}
+
+    def profile(self, enable: bool = True):
+        _check(lib().stencil_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int32()
+        _check(lib().stencil_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().stencil_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
