@@ -305,7 +305,9 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
             return hip_fail(e, "halo copy launch");
     }
     if (p->profiling && (e = hipEventRecord(p->ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    void *src = fields[0], *dst = fields[1];
+    // Jacobi kinds read fields[0] first; the leapfrog reads the newer level
+    // fields[1] and overwrites the older fields[0] in place.
+    void *src = wave ? fields[1] : fields[0], *dst = wave ? fields[0] : fields[1];
     for (int t = 0; t < iterations; ++t) {
         if (p->bc == STENCIL_BC_PERIODIC && (e = launch_periodic_fill(src, eb, p->g, p->rz, s)) != hipSuccess)
             return hip_fail(e, "periodic fill launch");
