@@ -118,6 +118,38 @@ def setup_workload(name, variant, dev, torch, synth, Plan):
                     iterations=T, bytes_per_update=16, kernel_tag=f"{name}_{variant}", source="heat.hip",
                     storage="f64")
         return plan, step, reset, pts * T, T, meta
+    if name == "copy":
+        # plain device-to-device copy of 1 GiB: the streaming ceiling, and the
+        # known-size kernel that calibrates the HBM byte counters
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+
+        class _CopyPlan:
+            def profile(self, on):
+                self.ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+            def profile_read(self):
+                self.ev[1].synchronize()
+                return self.ev[0].elapsed_time(self.ev[1]), 1
+
+            def config(self):
+                return {"tile": (0, 0, 0)}
+
+            def close(self):
+                pass
+
+        plan = _CopyPlan()
+
+        def step():
+            plan.ev[0].record()
+            dst.copy_(src)
+            plan.ev[1].record()
+            return None
+
+        meta = dict(workload="device copy, 1 GiB read + 1 GiB write (torch copy_)", interior=[nbytes // 8],
+                    iterations=1, bytes_per_update=16, kernel_tag="copy_1GiB", source="support.hip", storage="f64")
+        return plan, step, (lambda: None), nbytes // 8, 1, meta
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -160,7 +192,7 @@ def cpu_baseline(name):
         t = time.perf_counter()
         oracle.poisson19(p0, cf, 0.8, 2, mode="F32STORE")
         one = (time.perf_counter() - t) / 2
-        k = max(2, min(100, int(10.0 / max(one, 1e-3))))
+        k = max(2, min(2000, int(10.0 / max(one, 1e-3))))
         t = time.perf_counter()
         oracle.poisson19(p0, cf, 0.8, k, mode="F32STORE")
         dt = time.perf_counter() - t
@@ -172,7 +204,7 @@ def cpu_baseline(name):
         t = time.perf_counter()
         oracle.wave25(a, b, v, synth.WAVE25_COEF, 2)
         one = (time.perf_counter() - t) / 2
-        k = max(1, min(50, int(10.0 / max(one, 1e-3))))
+        k = max(1, min(500, int(10.0 / max(one, 1e-3))))
         t = time.perf_counter()
         oracle.wave25(a, b, v, synth.WAVE25_COEF, k)
         dt = time.perf_counter() - t
@@ -193,7 +225,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="poisson19", choices=["poisson19", "wave25", "heat2d5", "heat3d7"])
+    ap.add_argument("--workload", default="poisson19", choices=["poisson19", "wave25", "heat2d5", "heat3d7", "copy"])
     ap.add_argument("--variant", default="saturated", choices=["saturated", "plain"])
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain form beside it")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -254,7 +286,7 @@ def main():
         },
         "residual": main_r["resid"],
     }
-    if not a.no_plain and a.variant == "saturated" and a.workload != "heat2d5":
+    if not a.no_plain and a.variant == "saturated" and a.workload not in ("heat2d5", "copy"):
         pr = time_variant(a.workload, "plain", a.steps, a.warmup, dev, torch, synth, Plan)
         pv = pr["pts"] * a.steps / pr["wall"]
         pl = pr["sweep_ms"] / 1000.0 / max(1, pr["sweeps"])
@@ -262,7 +294,7 @@ def main():
                         "achieved_gbs": alg_bytes / pl / 1e9, "avg_launch_us": pl * 1e6,
                         "tile": list(pr["cfg"]["tile"])}
         out["saturated_over_plain"] = value / pv
-    if not a.no_cpu:
+    if not a.no_cpu and a.workload != "copy":
         out["cpu_baseline"] = cpu_baseline(a.workload)
     print(json.dumps(out), flush=True)
 
