@@ -170,6 +170,8 @@ stencil_status alloc_plan_buffers(stencil_plan_s *p) {
     p->nblocks = p->ops->nblocks(p->variant, p->tile, p->g);
     if ((e = hipMalloc(&p->d_part, sizeof(double) * (size_t)p->nblocks)) != hipSuccess)
         return fail(STENCIL_E_NOMEM, "hipMalloc residual partials (%lld blocks): %s", p->nblocks, hipGetErrorString(e));
+    if ((e = hipMalloc(&p->d_red, sizeof(double) * kReduceBlocks)) != hipSuccess)
+        return fail(STENCIL_E_NOMEM, "hipMalloc reduction scratch: %s", hipGetErrorString(e));
     if ((e = hipMalloc(&p->d_result, sizeof(double))) != hipSuccess)
         return fail(STENCIL_E_NOMEM, "hipMalloc result: %s", hipGetErrorString(e));
     if ((e = hipHostMalloc(&p->h_result, sizeof(double), hipHostMallocDefault)) != hipSuccess)
@@ -185,6 +187,7 @@ void free_plan(stencil_plan_s *p) {
     (void)hipGetDevice(&cur);
     if (p->device >= 0) (void)hipSetDevice(p->device);
     if (p->d_part) (void)hipFree(p->d_part);
+    if (p->d_red) (void)hipFree(p->d_red);
     if (p->d_result) (void)hipFree(p->d_result);
     if (p->h_result) (void)hipHostFree(p->h_result);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
@@ -254,6 +257,7 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out) {
     p->omega = d->omega;
     p->ops = ops_for(d->kind);
     for (int c = 0; c < 5; ++c) p->c[c] = (d->coef && c < d->n_coef) ? d->coef[c] : 0.0;
+    if (const char *e = std::getenv("STENCIL_XCD_REMAP")) p->remap = std::atoi(e) != 0;
     if ((e = hipGetDevice(&p->device)) != hipSuccess) {
         delete p;
         return hip_fail(e, "hipGetDevice");
@@ -281,6 +285,7 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
     a.g = p->g;
     for (int c = 0; c < 5; ++c) a.c[c] = p->c[c];
     a.omega = p->omega;
+    a.remap = p->remap;
     if (p->kind == STENCIL_POISSON19) {
         if (!coef_arrays) return fail(STENCIL_E_INVAL, "POISSON19 needs 12 coefficient arrays");
         for (int c = 0; c < 12; ++c) {
@@ -339,7 +344,7 @@ stencil_status stencil_residual(stencil_plan_t p, double *host_out, void *stream
     if (!guard.ok) return fail(STENCIL_E_DEVICE, "cannot make device %d current", p->device);
     hipStream_t s = (hipStream_t)stream_;
     hipError_t e;
-    if ((e = launch_reduce_partials(p->d_part, p->nblocks, p->d_result, s)) != hipSuccess)
+    if ((e = launch_reduce_partials(p->d_part, p->nblocks, p->d_red, p->d_result, s)) != hipSuccess)
         return hip_fail(e, "reduce launch");
     if ((e = hipMemcpyAsync(p->h_result, p->d_result, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync");

@@ -69,6 +69,25 @@ __device__ __forceinline__ int block_linear_id() {
     return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
 }
 
+// Workgroups are handed to the eight XCDs round-robin in dispatch order
+// (block L runs on XCD L % 8), and each XCD has its own L2.  With remap set,
+// logical tiles are renumbered so that every XCD receives one contiguous run
+// of them (x fastest, then y, then z): tiles that share halo rows, boundary
+// cache lines and priming planes then meet in the same L2.  The map is a
+// bijection of [0, N), so each tile is still computed exactly once.
+__device__ __forceinline__ void tile_coords(int remap, int &bx, int &by, int &bz) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    int L = block_linear_id();
+    if (remap) {
+        const int N = gx * gy * gridDim.z, q = N >> 3, rem = N & 7, x = L & 7;
+        L = x * q + min(x, rem) + (L >> 3);
+    }
+    bx = L % gx;
+    L /= gx;
+    by = L % gy;
+    bz = L / gy;
+}
+
 // ---------------------------------------------------------------------------
 // Halo stager: the cells of an xy tile's halo ring of width R (TX x TY
 // interior cells, LDS tile (TY+2R) x (TX+2R)), spread over the block's

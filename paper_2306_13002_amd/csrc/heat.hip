@@ -77,23 +77,25 @@ __global__ void heat3d7_plain(const double *__restrict__ src, double *__restrict
 // (ceil(nx/TX), ceil(ny/TY), ceil(nz/zb)).
 template <int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void heat3d7_sat(const double *__restrict__ src, double *__restrict__ dst,
-                                                      Geom g, double cc, double cn, int zb,
+                                                      Geom g, double cc, double cn, int zb, int remap,
                                                       double *__restrict__ part) {
     constexpr int R = 1, W = TX + 2 * R, NT = TX * TY;
     __shared__ double tile[2][(TY + 2 * R) * W];
     __shared__ double red[kMaxWaves];
+    int bx, by, bz;
+    tile_coords(remap, bx, by, bz);
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-    const int i = blockIdx.x * TX + tx, j = blockIdx.y * TY + ty;
+    const int i = bx * TX + tx, j = by * TY + ty;
     const int xp = i + R, yp = j + R;
     const int PX = g.nx + 2 * R, PY = g.ny + 2 * R, PZ = g.nz + 2 * R;
     const bool in = i < g.nx && j < g.ny;
     const bool ld = xp < PX && yp < PY;  // column inside the padded array (ring included)
-    const int k0 = blockIdx.z * zb, k1 = min(k0 + zb, g.nz);
+    const int k0 = bz * zb, k1 = min(k0 + zb, g.nz);
     const long long col = (long long)yp * g.py + xp;
     const int me = (ty + R) * W + (tx + R);
 
     HaloStager<double, TX, TY, R, false, NT> halo;
-    halo.init(tid, blockIdx.x * TX + R, blockIdx.y * TY + R, g.py, PX, PY);
+    halo.init(tid, bx * TX + R, by * TY + R, g.py, PX, PY);
 
     // padded z of the plane being computed: zc = k + R
     double prv = ld ? src[col + (long long)(k0)*g.pz] : 0.0;
@@ -177,7 +179,7 @@ hipError_t h3_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 #define X(A, B)                                                                                        \
     if (t.tx == A && t.ty == B) {                                                                      \
         hipLaunchKernelGGL((heat3d7_sat<A, B>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.c[0], a.c[1], \
-                           t.tz, a.part);                                                              \
+                           t.tz, a.remap, a.part);                                                     \
         return hipGetLastError();                                                                      \
     }
     HEAT3D7_SAT_TILES(X)

@@ -28,6 +28,7 @@ struct SweepArgs {
     const int *taps;          // GENERIC: device tap table
     const double *tap_coef;   // GENERIC: device coefficient table
     int n_taps, n_coef;
+    int remap;                // saturated forms: XCD-chunked block -> tile map (1) or natural order (0)
 };
 
 struct KindOps {
@@ -42,7 +43,10 @@ extern KindOps heat2d5_ops, heat3d7_ops, poisson19_ops, wave25_ops;
 hipError_t launch_halo_copy(const void *src, void *dst, int elem_bytes, const Geom &g, int rz, hipStream_t s);
 hipError_t launch_periodic_fill(void *buf, int elem_bytes, const Geom &g, int rz, hipStream_t s);
 hipError_t launch_interior_copy(const void *src, void *dst, int elem_bytes, const Geom &g, int rz, hipStream_t s);
-hipError_t launch_reduce_partials(const double *part, long long n, double *out, hipStream_t s);
+// Two fixed-order passes: up to kReduceBlocks blocks each sum a contiguous
+// chunk of part[] into scratch[], then one block sums scratch[].
+constexpr int kReduceBlocks = 256;
+hipError_t launch_reduce_partials(const double *part, long long n, double *scratch, double *out, hipStream_t s);
 
 inline long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 

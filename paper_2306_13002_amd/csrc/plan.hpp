@@ -18,6 +18,8 @@ struct stencil_plan_s {
     int device = -1;
     long long nblocks = 0;      // blocks of one sweep launch = residual partial count
     double *d_part = nullptr;   // device: per-block residual partials of the last sweep
+    double *d_red = nullptr;    // device: first-pass sums of the residual reduction
+    int remap = 1;              // XCD-chunked tile order for the saturated forms
     double *d_result = nullptr; // device: reduced residual
     double *h_result = nullptr; // pinned host copy
     bool has_resid = false;

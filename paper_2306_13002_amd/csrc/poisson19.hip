@@ -80,23 +80,25 @@ __global__ void poisson19_plain(const float *__restrict__ p, float *__restrict__
 
 template <int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void poisson19_sat(const float *__restrict__ p, float *__restrict__ pn,
-                                                        P19Coef c, Geom g, double omega, int zb,
+                                                        P19Coef c, Geom g, double omega, int zb, int remap,
                                                         double *__restrict__ part) {
     constexpr int R = 1, W = TX + 2 * R, NT = TX * TY, PLANE = (TY + 2 * R) * W;
     __shared__ float ring[4][PLANE];
     __shared__ double red[kMaxWaves];
+    int bx, by, bz;
+    tile_coords(remap, bx, by, bz);
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-    const int i = blockIdx.x * TX + tx, j = blockIdx.y * TY + ty;
+    const int i = bx * TX + tx, j = by * TY + ty;
     const int xp = i + R, yp = j + R;
     const int PX = g.nx + 2 * R, PY = g.ny + 2 * R;
     const bool in = i < g.nx && j < g.ny;
     const bool ld = xp < PX && yp < PY;
-    const int k0 = blockIdx.z * zb, k1 = min(k0 + zb, g.nz);
+    const int k0 = bz * zb, k1 = min(k0 + zb, g.nz);
     const long long col = (long long)yp * g.py + xp;
     const int me = (ty + R) * W + (tx + R);
 
     HaloStager<float, TX, TY, R, true, NT> halo;
-    halo.init(tid, blockIdx.x * TX + R, blockIdx.y * TY + R, g.py, PX, PY);
+    halo.init(tid, bx * TX + R, by * TY + R, g.py, PX, PY);
 
     // prologue: planes zc0-1 and zc0 (zc = k + 1) into the ring
     for (int z = k0; z <= k0 + 1; ++z) {
@@ -194,7 +196,7 @@ hipError_t p19_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 #define X(A, B)                                                                                          \
     if (t.tx == A && t.ty == B) {                                                                        \
         hipLaunchKernelGGL((poisson19_sat<A, B>), grid, dim3(A, B, 1), 0, s, src, dst, c, a.g, a.omega, t.tz, \
-                           a.part);                                                                      \
+                           a.remap, a.part);                                                             \
         return hipGetLastError();                                                                        \
     }
     P19_SAT_TILES(X)

@@ -78,12 +78,17 @@ __global__ void interior_copy_kernel(const T *__restrict__ src, T *__restrict__ 
     }
 }
 
-__global__ void reduce_partials_kernel(const double *__restrict__ part, long long n, double *__restrict__ out) {
+// Pass 1: block b sums the contiguous chunk [b*chunk, min((b+1)*chunk, n))
+// (thread-strided, then the block sum); pass 2 (one block) sums the pass-1
+// results.  The split depends only on n, so the total is reproducible.
+__global__ void reduce_pass1_kernel(const double *__restrict__ part, long long n, long long chunk,
+                                    double *__restrict__ out) {
     __shared__ double lds[4];
+    const long long b0 = blockIdx.x * chunk, b1 = min(b0 + chunk, n);
     double s = 0.0;
-    for (long long i = threadIdx.x; i < n; i += 256) s += part[i];
+    for (long long i = b0 + threadIdx.x; i < b1; i += 256) s += part[i];
     s = block_sum_f64(s, lds);
-    if (threadIdx.x == 0) out[0] = s;
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 dim3 grid_for(long long n) {
@@ -130,8 +135,14 @@ hipError_t launch_interior_copy(const void *src, void *dst, int eb, const Geom &
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_partials(const double *part, long long n, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, part, n, out);
+hipError_t launch_reduce_partials(const double *part, long long n, double *scratch, double *out, hipStream_t s) {
+    long long chunk = cdiv(n, kReduceBlocks);
+    if (chunk < 1024) chunk = 1024;
+    const long long nb = cdiv(n, chunk);
+    hipLaunchKernelGGL(reduce_pass1_kernel, dim3((unsigned)nb), dim3(256), 0, s, part, n, chunk, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_pass1_kernel, dim3(1), dim3(256), 0, s, (const double *)scratch, nb, nb, out);
     return hipGetLastError();
 }
 

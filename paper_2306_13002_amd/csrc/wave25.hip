@@ -84,15 +84,17 @@ __global__ void wave25_plain(const double *__restrict__ cur, double *__restrict_
 template <int TX, int BY, int RY>
 __global__ __launch_bounds__(TX *BY) void wave25_sat(const double *__restrict__ cur, double *__restrict__ pn,
                                                      const double *__restrict__ vsq, Geom g, W25C c, int zb,
-                                                     double *__restrict__ part) {
+                                                     int remap, double *__restrict__ part) {
     constexpr int R = 4, TY = BY * RY, W = TX + 2 * R, NT = TX * BY, PLANE = (TY + 2 * R) * W;
     __shared__ double tile[2][PLANE];
     __shared__ double red[kMaxWaves];
+    int bx, by, bz;
+    tile_coords(remap, bx, by, bz);
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-    const int i = blockIdx.x * TX + tx, jb = blockIdx.y * TY + ty * RY;
+    const int i = bx * TX + tx, jb = by * TY + ty * RY;
     const int xp = i + R;
     const int PX = g.nx + 2 * R, PY = g.ny + 2 * R, PZ = g.nz + 2 * R;
-    const int k0 = blockIdx.z * zb, k1 = min(k0 + zb, g.nz);
+    const int k0 = bz * zb, k1 = min(k0 + zb, g.nz);
 
     bool in[RY], ld[RY];
     long long col[RY];
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(TX *BY) void wave25_sat(const double *__restrict__ 
         me[m] = (ty * RY + m + R) * W + (tx + R);
     }
     HaloStager<double, TX, TY, R, false, NT> halo;
-    halo.init(tid, blockIdx.x * TX + R, blockIdx.y * TY + R, g.py, PX, PY);
+    halo.init(tid, bx * TX + R, by * TY + R, g.py, PX, PY);
 
     // q[m][s] = u^n at padded z = zc - 4 + s, zc = k + 4 the plane computed
     double q[RY][9], up[RY], vv[RY];
@@ -212,7 +214,7 @@ hipError_t w25_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 #define X(A, TY, BY, RY)                                                                                   \
     if (t.tx == A && t.ty == TY) {                                                                         \
         hipLaunchKernelGGL((wave25_sat<A, BY, RY>), grid, dim3(A, BY, 1), 0, s, cur, pn, vsq, a.g, c, t.tz, \
-                           a.part);                                                                        \
+                           a.remap, a.part);                                                               \
         return hipGetLastError();                                                                          \
     }
     W25_SAT_TILES(X)
