@@ -121,7 +121,9 @@ typedef struct {
     int32_t tile_x;         /* threads along x per block; 0 = let the plan decide */
     int32_t tile_y;         /* rows per block tile; 0 = let the plan decide */
     int32_t zblock;         /* z planes per block (saturated forms); 0 = let the plan decide */
-    int32_t reserved;
+    int32_t tile_map;       /* saturated forms, order of blocks over tiles: 0 = let the plan decide,
+                               1 = natural (x fastest), 2 = XCD-chunked (each of the 8 XCDs gets one
+                               contiguous run of tiles, so neighbours share an L2) */
 } stencil_desc;
 
 /* Build a plan: validate d (host only, no device call before validation
@@ -152,9 +154,10 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
  * synchronizes `stream`.  E_STATE if no sweep has run on this plan. */
 stencil_status stencil_residual(stencil_plan_t p, double *host_out, void *stream);
 
-/* Chosen configuration of a plan (any output pointer may be NULL). */
+/* Chosen configuration of a plan (any output pointer may be NULL).
+ * tile_map is reported as 1 (natural) or 2 (XCD-chunked). */
 stencil_status stencil_plan_config(stencil_plan_t p, int32_t *variant, int32_t *tile_x, int32_t *tile_y,
-                                   int32_t *zblock);
+                                   int32_t *zblock, int32_t *tile_map);
 
 /* Sweep timing.  When enabled, stencil_run records HIP events on its stream
  * around its sweep launches (after the halo copy, before any tail copy);

@@ -18,6 +18,7 @@
 #include "../../include/stencil.h"
 #include "internal.hpp"
 #include "plan.hpp"
+#include "tune.hpp"
 
 using namespace stn;
 
@@ -75,16 +76,19 @@ const KindOps *ops_for(int kind) {
 
 int elem_bytes(int dtype) { return dtype == STENCIL_F32 ? 4 : 8; }
 
-// Library defaults (used when a tile field is 0 and tuning is FIXED).
+// Library defaults (used when a field is left open and tuning is FIXED);
+// picked from launch-shape sweeps on MI355X at the workload sizes.
 Tile default_tile(int kind, int variant, const Geom &g) {
-    if (variant == V_PLAIN) return kind == STENCIL_HEAT2D5 ? Tile{64, 4, 1} : Tile{64, 4, 1};
+    if (variant == V_PLAIN) return kind == STENCIL_HEAT2D5 ? Tile{64, 4, 1} : Tile{128, 8, 1};
     switch (kind) {
-    case STENCIL_HEAT3D7: return Tile{64, 4, g.nz < 64 ? g.nz : 64};
-    case STENCIL_POISSON19: return Tile{64, 4, 16};
-    case STENCIL_WAVE25: return Tile{64, 8, 64};
+    case STENCIL_HEAT3D7: return Tile{32, 8, g.nz < 8 ? g.nz : 8};
+    case STENCIL_POISSON19: return Tile{128, 4, g.nz < 32 ? g.nz : 32};
+    case STENCIL_WAVE25: return Tile{128, 8, g.nz < 128 ? g.nz : 128};
     default: return Tile{64, 4, 16};
     }
 }
+
+int default_remap(int kind) { return kind == STENCIL_WAVE25 ? 0 : 1; }
 
 // Validate the descriptor (host only).  Fills geometry on success.
 stencil_status validate_desc(const stencil_desc *d, Geom &g, int &rz) {
@@ -212,11 +216,28 @@ struct DeviceGuard {
 
 stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     const KindOps *ops = p->ops;
-    const bool has_sat = ops->tile_ok(V_SATURATED, default_tile(p->kind, V_SATURATED, p->g));
+    const bool has_sat = ops->sat_tiles != nullptr;
+    if (d->tile_map < 0 || d->tile_map > 2) return fail(STENCIL_E_INVAL, "tile_map %d not in 0..2", d->tile_map);
+    if (d->variant == STENCIL_SATURATED && !has_sat)
+        return fail(STENCIL_E_UNSUPPORTED, "kind %d has no saturated form", p->kind);
+    const bool open = d->variant == STENCIL_AUTO || !d->tile_x || !d->tile_y || !d->zblock || !d->tile_map;
+    if (d->tune == STENCIL_TUNE_EXHAUSTIVE && open) {
+        TuneRequest rq{has_sat ? d->variant : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map};
+        const std::string key = tune_key(p, rq);
+        TuneEntry e{};
+        if (!tune_lookup(key, &e)) {
+            stencil_status st = tune_exhaustive(p, rq, &e);
+            if (st != STENCIL_OK) return st;
+            tune_store(key, e);
+        }
+        p->variant = e.variant;
+        p->tile = e.tile;
+        p->remap = e.remap;
+        p->tuned = true;
+        return STENCIL_OK;
+    }
     int v = d->variant;
     if (v == STENCIL_AUTO) v = has_sat ? V_SATURATED : V_PLAIN;
-    if (v == V_SATURATED && !has_sat)
-        return fail(STENCIL_E_UNSUPPORTED, "kind %d has no saturated form", p->kind);
     Tile t = default_tile(p->kind, v, p->g);
     if (d->tile_x) t.tx = d->tile_x;
     if (d->tile_y) t.ty = d->tile_y;
@@ -226,6 +247,7 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
                     p->kind, v);
     p->variant = v;
     p->tile = t;
+    p->remap = d->tile_map ? (d->tile_map == 2) : default_remap(p->kind);
     return STENCIL_OK;
 }
 
@@ -241,8 +263,8 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out) {
     stencil_status st = validate_desc(d, g, rz);
     if (st != STENCIL_OK) return st;
     if (d->kind == STENCIL_GENERIC) return fail(STENCIL_E_UNSUPPORTED, "GENERIC stencils are not built into this library yet");
-    if (d->tune != STENCIL_TUNE_FIXED)
-        return fail(STENCIL_E_UNSUPPORTED, "tune mode %d is not available in this build", d->tune);
+    if (d->tune == STENCIL_TUNE_MODEL)
+        return fail(STENCIL_E_UNSUPPORTED, "tune mode MODEL is not available in this build");
     // device
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -257,7 +279,9 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out) {
     p->omega = d->omega;
     p->ops = ops_for(d->kind);
     for (int c = 0; c < 5; ++c) p->c[c] = (d->coef && c < d->n_coef) ? d->coef[c] : 0.0;
-    if (const char *e = std::getenv("STENCIL_XCD_REMAP")) p->remap = std::atoi(e) != 0;
+    p->base_args.g = g;
+    for (int c = 0; c < 5; ++c) p->base_args.c[c] = p->c[c];
+    p->base_args.omega = d->omega;
     if ((e = hipGetDevice(&p->device)) != hipSuccess) {
         delete p;
         return hip_fail(e, "hipGetDevice");
@@ -266,8 +290,8 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out) {
         free_plan(p);
         return st;
     }
-    logf("plan kind=%d variant=%d tile=(%d,%d,%d) n=(%d,%d,%d) blocks=%lld", p->kind, p->variant, p->tile.tx,
-         p->tile.ty, p->tile.tz, g.nx, g.ny, g.nz, p->nblocks);
+    logf("plan kind=%d variant=%d tile=(%d,%d,%d) map=%d tuned=%d n=(%d,%d,%d) blocks=%lld", p->kind, p->variant,
+         p->tile.tx, p->tile.ty, p->tile.tz, p->remap ? 2 : 1, (int)p->tuned, g.nx, g.ny, g.nz, p->nblocks);
     *out = p;
     return STENCIL_OK;
 }
@@ -281,10 +305,7 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
     const int eb = elem_bytes(p->dtype);
     for (int f = 0; f < 2; ++f)
         if ((uintptr_t)fields[f] % eb) return fail(STENCIL_E_INVAL, "fields[%d] is not %d-byte aligned", f, eb);
-    SweepArgs a{};
-    a.g = p->g;
-    for (int c = 0; c < 5; ++c) a.c[c] = p->c[c];
-    a.omega = p->omega;
+    SweepArgs a = p->base_args;
     a.remap = p->remap;
     if (p->kind == STENCIL_POISSON19) {
         if (!coef_arrays) return fail(STENCIL_E_INVAL, "POISSON19 needs 12 coefficient arrays");
@@ -354,12 +375,13 @@ stencil_status stencil_residual(stencil_plan_t p, double *host_out, void *stream
 }
 
 stencil_status stencil_plan_config(stencil_plan_t p, int32_t *variant, int32_t *tile_x, int32_t *tile_y,
-                                   int32_t *zblock) {
+                                   int32_t *zblock, int32_t *tile_map) {
     if (!p) return fail(STENCIL_E_INVAL, "plan is NULL");
     if (variant) *variant = p->variant;
     if (tile_x) *tile_x = p->tile.tx;
     if (tile_y) *tile_y = p->tile.ty;
     if (zblock) *zblock = p->tile.tz;
+    if (tile_map) *tile_map = p->remap ? 2 : 1;
     return STENCIL_OK;
 }
 

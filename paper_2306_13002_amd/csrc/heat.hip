@@ -163,6 +163,14 @@ bool h3_tile_ok(int v, Tile t) {
     return false;
 }
 
+int h3_sat_tiles(Tile *out, int max) {
+    int n = 0;
+#define X(a, b) if (n < max) out[n++] = Tile{a, b, 0};
+    HEAT3D7_SAT_TILES(X)
+#undef X
+    return n;
+}
+
 long long h3_nblocks(int v, Tile t, const Geom &g) {
     return cdiv(g.nx, t.tx) * cdiv(g.ny, t.ty) * cdiv(g.nz, t.tz);
 }
@@ -189,7 +197,7 @@ hipError_t h3_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 
 }  // namespace
 
-KindOps heat2d5_ops = {h2_tile_ok, h2_nblocks, h2_launch};
-KindOps heat3d7_ops = {h3_tile_ok, h3_nblocks, h3_launch};
+KindOps heat2d5_ops = {h2_tile_ok, nullptr, h2_nblocks, h2_launch};
+KindOps heat3d7_ops = {h3_tile_ok, h3_sat_tiles, h3_nblocks, h3_launch};
 
 }  // namespace stn

@@ -33,6 +33,7 @@ struct SweepArgs {
 
 struct KindOps {
     bool (*tile_ok)(int variant, Tile t);
+    int (*sat_tiles)(Tile *out, int max);  // offered saturated (tx, ty) shapes; nullptr if none
     long long (*nblocks)(int variant, Tile t, const Geom &g);
     hipError_t (*launch)(int variant, Tile t, const SweepArgs &a, hipStream_t s);
 };
@@ -42,6 +43,7 @@ extern KindOps heat2d5_ops, heat3d7_ops, poisson19_ops, wave25_ops;
 // Support kernels (support.hip).
 hipError_t launch_halo_copy(const void *src, void *dst, int elem_bytes, const Geom &g, int rz, hipStream_t s);
 hipError_t launch_periodic_fill(void *buf, int elem_bytes, const Geom &g, int rz, hipStream_t s);
+hipError_t launch_fill(void *buf, long long n, int elem_bytes, double value, hipStream_t s);
 hipError_t launch_interior_copy(const void *src, void *dst, int elem_bytes, const Geom &g, int rz, hipStream_t s);
 // Two fixed-order passes: up to kReduceBlocks blocks each sum a contiguous
 // chunk of part[] into scratch[], then one block sums scratch[].

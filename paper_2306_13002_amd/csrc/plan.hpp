@@ -26,4 +26,7 @@ struct stencil_plan_s {
     bool profiling = false, prof_valid = false;
     int prof_sweeps = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    stn::SweepArgs base_args{};  // geometry and scalars shared by every launch of this plan
+    unsigned taps_hash = 0;      // GENERIC: hash of the tap pattern (part of the tune key)
+    bool tuned = false;          // configuration came from the autotuner
 };

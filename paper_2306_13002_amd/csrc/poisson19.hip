@@ -182,6 +182,14 @@ bool p19_tile_ok(int v, Tile t) {
     return false;
 }
 
+int p19_sat_tiles(Tile *out, int max) {
+    int n = 0;
+#define X(a, b) if (n < max) out[n++] = Tile{a, b, 0};
+    P19_SAT_TILES(X)
+#undef X
+    return n;
+}
+
 long long p19_nblocks(int, Tile t, const Geom &g) { return cdiv(g.nx, t.tx) * cdiv(g.ny, t.ty) * cdiv(g.nz, t.tz); }
 
 hipError_t p19_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
@@ -206,6 +214,6 @@ hipError_t p19_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 
 }  // namespace
 
-KindOps poisson19_ops = {p19_tile_ok, p19_nblocks, p19_launch};
+KindOps poisson19_ops = {p19_tile_ok, p19_sat_tiles, p19_nblocks, p19_launch};
 
 }  // namespace stn

@@ -91,6 +91,12 @@ __global__ void reduce_pass1_kernel(const double *__restrict__ part, long long n
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+template <typename T>
+__global__ void fill_kernel(T *__restrict__ buf, long long n, T v) {
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+        buf[t] = v;
+}
+
 dim3 grid_for(long long n) {
     long long b = cdiv(n, 256);
     if (b > 65536) b = 65536;
@@ -119,6 +125,14 @@ hipError_t launch_periodic_fill(void *buf, int eb, const Geom &g, int rz, hipStr
         hipLaunchKernelGGL(periodic_fill_kernel<double>, grid_for(n), dim3(256), 0, s, (double *)buf, g, rz, n);
     else
         hipLaunchKernelGGL(periodic_fill_kernel<float>, grid_for(n), dim3(256), 0, s, (float *)buf, g, rz, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(void *buf, long long n, int eb, double v, hipStream_t s) {
+    if (eb == 8)
+        hipLaunchKernelGGL(fill_kernel<double>, grid_for(n), dim3(256), 0, s, (double *)buf, n, v);
+    else
+        hipLaunchKernelGGL(fill_kernel<float>, grid_for(n), dim3(256), 0, s, (float *)buf, n, (float)v);
     return hipGetLastError();
 }
 

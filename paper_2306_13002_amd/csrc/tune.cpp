@@ -1,0 +1,240 @@
+// tune.cpp -- exhaustive autotuner for stencil plans.
+//
+// For a plan's kind, dtype, boundary and geometry it enumerates every
+// offered (variant, tile, zblock, tile map) that the descriptor leaves open,
+// runs each on private buffers of the same layout (filled with benign
+// constants) on a private stream, and keeps the candidate with the lowest
+// median time per sweep.  Results are cached per geometry in-process and,
+// when STENCIL_TUNE_CACHE names a file, in that file as JSON lines that a
+// later process reloads verbatim.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/stencil.h"
+#include "internal.hpp"
+#include "plan.hpp"
+#include "tune.hpp"
+
+namespace stn {
+
+stencil_status fail(stencil_status st, const char *fmt, ...);
+void logf(const char *fmt, ...);
+stencil_status hip_fail(hipError_t e, const char *what);
+int elem_bytes(int dtype);
+
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, TuneEntry> g_cache;
+bool g_file_loaded = false;
+
+const char *cache_path() {
+    const char *e = std::getenv("STENCIL_TUNE_CACHE");
+    return (e && *e) ? e : nullptr;
+}
+
+void load_file_locked() {
+    if (g_file_loaded) return;
+    g_file_loaded = true;
+    const char *path = cache_path();
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[1024], key[512];
+    while (std::fgets(line, sizeof line, f)) {
+        TuneEntry e{};
+        // {"key": "...", "variant": V, "tx": X, "ty": Y, "zb": Z, "map": M, "us": U}
+        if (std::sscanf(line, " {\"key\": \"%511[^\"]\", \"variant\": %d, \"tx\": %d, \"ty\": %d, \"zb\": %d, "
+                              "\"map\": %d, \"us\": %lf}",
+                        key, &e.variant, &e.tile.tx, &e.tile.ty, &e.tile.tz, &e.remap, &e.us) == 7)
+            g_cache[key] = e;
+    }
+    std::fclose(f);
+}
+
+void append_file_locked(const std::string &key, const TuneEntry &e) {
+    const char *path = cache_path();
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "{\"key\": \"%s\", \"variant\": %d, \"tx\": %d, \"ty\": %d, \"zb\": %d, \"map\": %d, \"us\": %.4f}\n",
+                 key.c_str(), e.variant, e.tile.tx, e.tile.ty, e.tile.tz, e.remap, e.us);
+    std::fclose(f);
+}
+
+const Tile kPlainTiles[] = {{64, 4, 1},  {64, 2, 2},  {128, 2, 1}, {256, 1, 1}, {32, 8, 1},
+                            {64, 8, 1},  {128, 4, 1}, {128, 8, 1}, {256, 2, 1}};
+const int kZblocks[] = {4, 8, 16, 32, 64, 128, 256};
+
+struct Cand {
+    int variant;
+    Tile tile;
+    int remap;
+};
+
+std::vector<Cand> candidates(const stencil_plan_s *p, const TuneRequest &rq) {
+    std::vector<Cand> out;
+    const KindOps *ops = p->ops;
+    auto want_v = [&](int v) { return rq.variant == STENCIL_AUTO || rq.variant == v; };
+    auto tile_fits = [&](const Tile &t) {
+        return (!rq.tile_x || rq.tile_x == t.tx) && (!rq.tile_y || rq.tile_y == t.ty) &&
+               (!rq.zblock || rq.zblock == t.tz);
+    };
+    if (want_v(V_PLAIN))
+        for (const Tile &t : kPlainTiles)
+            if (ops->tile_ok(V_PLAIN, t) && tile_fits(t)) out.push_back({V_PLAIN, t, 1});
+    if (want_v(V_SATURATED) && ops->sat_tiles) {
+        Tile st[64];
+        const int ns = ops->sat_tiles(st, 64);
+        std::vector<int> zbs;
+        for (int zb : kZblocks)
+            if (zb < p->g.nz) zbs.push_back(zb);
+        zbs.push_back(p->g.nz);
+        for (int s = 0; s < ns; ++s)
+            for (int zb : zbs) {
+                Tile t{st[s].tx, st[s].ty, zb};
+                if (!ops->tile_ok(V_SATURATED, t) || !tile_fits(t)) continue;
+                for (int m = 1; m <= 2; ++m)
+                    if (!rq.tile_map || rq.tile_map == m) out.push_back({V_SATURATED, t, m == 2 ? 1 : 0});
+            }
+    }
+    return out;
+}
+
+struct Buffers {
+    void *f[2] = {nullptr, nullptr};
+    void *c[12] = {};
+    int nc = 0;
+    ~Buffers() {
+        for (void *q : f)
+            if (q) (void)hipFree(q);
+        for (void *q : c)
+            if (q) (void)hipFree(q);
+    }
+};
+
+}  // namespace
+
+std::string tune_key(const stencil_plan_s *p, const TuneRequest &rq) {
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "k%d/d%d/bc%d/n%dx%dx%d/r%d/py%lld/pz%lld/v%d/t%d,%d,%d,%d/h%08x", p->kind,
+                  p->dtype, p->bc, p->g.nx, p->g.ny, p->g.nz, p->g.r, p->g.py, p->g.pz, rq.variant, rq.tile_x,
+                  rq.tile_y, rq.zblock, rq.tile_map, p->taps_hash);
+    return buf;
+}
+
+bool tune_lookup(const std::string &key, TuneEntry *out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_file_locked();
+    auto it = g_cache.find(key);
+    if (it == g_cache.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void tune_store(const std::string &key, const TuneEntry &e) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_file_locked();
+    g_cache[key] = e;
+    append_file_locked(key, e);
+}
+
+// Time one candidate: T sweeps back to back, `reps` times; median per sweep (us).
+static double time_one(const stencil_plan_s *p, const Cand &c, Buffers &b, hipStream_t s, hipEvent_t e0,
+                       hipEvent_t e1, int T, int reps, hipError_t *err) {
+    SweepArgs a = p->base_args;
+    a.remap = c.remap;
+    a.part = nullptr;
+    for (int i = 0; i < b.nc; ++i) a.coefs[i] = b.c[i];
+    std::vector<double> ts;
+    const bool wave = p->kind == STENCIL_WAVE25;
+    for (int r = 0; r < reps + 1; ++r) {  // first repetition warms up
+        void *src = wave ? b.f[1] : b.f[0], *dst = wave ? b.f[0] : b.f[1];
+        if ((*err = hipEventRecord(e0, s)) != hipSuccess) return 0;
+        for (int t = 0; t < T; ++t) {
+            a.src = src;
+            a.dst = dst;
+            if ((*err = p->ops->launch(c.variant, c.tile, a, s)) != hipSuccess) return 0;
+            std::swap(src, dst);
+        }
+        if ((*err = hipEventRecord(e1, s)) != hipSuccess) return 0;
+        if ((*err = hipEventSynchronize(e1)) != hipSuccess) return 0;
+        float ms = 0;
+        if ((*err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return 0;
+        if (r > 0) ts.push_back(1e3 * ms / T);
+    }
+    std::sort(ts.begin(), ts.end());
+    return ts[ts.size() / 2];
+}
+
+stencil_status tune_exhaustive(stencil_plan_s *p, const TuneRequest &rq, TuneEntry *best) {
+    const std::vector<Cand> cands = candidates(p, rq);
+    if (cands.empty()) return fail(STENCIL_E_UNSUPPORTED, "no launch shape matches the requested tile fields");
+    const int eb = elem_bytes(p->dtype);
+    const long long span = (long long)(p->g.PZ() - 1) * p->g.pz * (p->rz ? 1 : 0) +
+                           (long long)(p->g.PY() - 1) * p->g.py + p->g.PX();
+    const size_t bytes = (size_t)span * eb;
+    Buffers b;
+    hipError_t e;
+    for (int i = 0; i < 2; ++i)
+        if ((e = hipMalloc(&b.f[i], bytes)) != hipSuccess) return fail(STENCIL_E_NOMEM, "tuner buffers: %s", hipGetErrorString(e));
+    b.nc = p->kind == STENCIL_POISSON19 ? 12 : (p->kind == STENCIL_WAVE25 ? 1 : 0);
+    const size_t cb = p->kind == STENCIL_POISSON19 ? (size_t)span * 4 : bytes;
+    for (int i = 0; i < b.nc; ++i)
+        if ((e = hipMalloc(&b.c[i], cb)) != hipSuccess) return fail(STENCIL_E_NOMEM, "tuner buffers: %s", hipGetErrorString(e));
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((e = hipStreamCreate(&s)) != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    struct Cleanup {
+        hipStream_t s;
+        hipEvent_t *a, *b;
+        ~Cleanup() {
+            if (*a) (void)hipEventDestroy(*a);
+            if (*b) (void)hipEventDestroy(*b);
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } cleanup{s, &e0, &e1};
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+        return hip_fail(e, "hipEventCreate");
+    // benign values: the state stays bounded under every kind's update
+    const double fv = 1.0;
+    for (int i = 0; i < 2; ++i)
+        if ((e = launch_fill(b.f[i], span, eb, fv, s)) != hipSuccess) return hip_fail(e, "fill");
+    for (int i = 0; i < b.nc; ++i) {
+        const double cv = p->kind == STENCIL_WAVE25 ? 0.01 : 0.1;
+        if ((e = launch_fill(b.c[i], span, p->kind == STENCIL_POISSON19 ? 4 : eb, cv, s)) != hipSuccess)
+            return hip_fail(e, "fill");
+    }
+    // sweeps per timing: about 1 ms of work per repetition, 2..50 sweeps
+    hipError_t te = hipSuccess;
+    double probe = time_one(p, cands[0], b, s, e0, e1, 2, 1, &te);
+    if (te != hipSuccess) return hip_fail(te, "tuner launch");
+    int T = (int)std::min(50.0, std::max(2.0, 1000.0 / std::max(probe, 1.0)));
+    TuneEntry bestv{};
+    bestv.us = 1e300;
+    for (const Cand &c : cands) {
+        const double us = time_one(p, c, b, s, e0, e1, T, 3, &te);
+        if (te != hipSuccess) return hip_fail(te, "tuner launch");
+        logf("tune kind=%d v=%d tile=(%d,%d,%d) map=%d: %.2f us/sweep", p->kind, c.variant, c.tile.tx, c.tile.ty,
+             c.tile.tz, c.remap ? 2 : 1, us);
+        if (us < bestv.us) {
+            bestv.us = us;
+            bestv.variant = c.variant;
+            bestv.tile = c.tile;
+            bestv.remap = c.remap;
+        }
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    *best = bestv;
+    return STENCIL_OK;
+}
+
+}  // namespace stn

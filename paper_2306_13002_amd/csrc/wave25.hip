@@ -199,6 +199,14 @@ bool w25_tile_ok(int v, Tile t) {
     return false;
 }
 
+int w25_sat_tiles(Tile *out, int max) {
+    int n = 0;
+#define X(A_, TY_, BY_, RY_) if (n < max) out[n++] = Tile{A_, TY_, 0};
+    W25_SAT_TILES(X)
+#undef X
+    return n;
+}
+
 long long w25_nblocks(int, Tile t, const Geom &g) { return cdiv(g.nx, t.tx) * cdiv(g.ny, t.ty) * cdiv(g.nz, t.tz); }
 
 hipError_t w25_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
@@ -224,6 +232,6 @@ hipError_t w25_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 
 }  // namespace
 
-KindOps wave25_ops = {w25_tile_ok, w25_nblocks, w25_launch};
+KindOps wave25_ops = {w25_tile_ok, w25_sat_tiles, w25_nblocks, w25_launch};
 
 }  // namespace stn

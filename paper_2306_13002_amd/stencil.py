@@ -23,6 +23,8 @@ VARIANTS = {"plain": 0, "saturated": 1, "auto": 2}
 VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
 TUNES = {"fixed": 0, "exhaustive": 1, "model": 2}
 BCS = {"dirichlet": 0, "periodic": 1}
+TILE_MAPS = {"auto": 0, "natural": 1, "xcd": 2}
+TILE_MAP_NAMES = {1: "natural", 2: "xcd"}
 RADIUS = {"heat2d5": 1, "heat3d7": 1, "poisson19": 1, "wave25": 4}
 DEFAULT_DTYPE = {"heat2d5": "f64", "heat3d7": "f64", "poisson19": "f32", "wave25": "f64", "generic": "f64"}
 
@@ -37,7 +39,7 @@ class StencilDesc(ctypes.Structure):
         ("n_taps", ctypes.c_int32), ("tap_off", ctypes.POINTER(ctypes.c_int32)),
         ("tap_cid", ctypes.POINTER(ctypes.c_int32)), ("omega", ctypes.c_double),
         ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("zblock", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("tile_map", ctypes.c_int32),
     ]
 
 
@@ -62,7 +64,7 @@ def lib():
         L.stencil_plan.argtypes = [ctypes.POINTER(StencilDesc), ctypes.POINTER(vp)]
         L.stencil_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
         L.stencil_residual.argtypes = [vp, dp, vp]
-        L.stencil_plan_config.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
+        L.stencil_plan_config.argtypes = [vp] + [ctypes.POINTER(i32)] * 5
         L.stencil_profile_enable.argtypes = [vp, i32]
         L.stencil_profile_read.argtypes = [vp, dp, ctypes.POINTER(i32)]
         L.stencil_destroy.argtypes = [vp]
@@ -90,7 +92,7 @@ def make_desc(kind: str, n: Sequence[int], dtype: Optional[str] = None, variant:
               tune: str = "fixed", bc: str = "dirichlet", coef: Optional[Sequence[float]] = None,
               taps: Optional[Sequence[Sequence[int]]] = None, cids: Optional[Sequence[int]] = None,
               radius: Optional[int] = None, omega: float = 0.8, tile: Sequence[int] = (0, 0, 0),
-              pitch: Sequence[int] = (0, 0)):
+              pitch: Sequence[int] = (0, 0), tile_map: str = "auto"):
     """Pack a stencil_desc.  Returns (desc, keepalive) -- keep the second
     object alive until stencil_plan has copied the host arrays."""
     d = StencilDesc()
@@ -122,6 +124,7 @@ def make_desc(kind: str, n: Sequence[int], dtype: Optional[str] = None, variant:
         d.n_taps = len(taps)
     d.omega = float(omega)
     d.tile_x, d.tile_y, d.zblock = (int(v) for v in tile)
+    d.tile_map = TILE_MAPS[tile_map]
     return d, keep
 
 
@@ -215,9 +218,11 @@ class Plan:
         return out.value
 
     def config(self) -> dict:
-        v, tx, ty, zb = (ctypes.c_int32() for _ in range(4))
-        _check(lib().stencil_plan_config(self._h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(zb)))
-        return {"variant": VARIANT_NAMES[v.value], "tile": (tx.value, ty.value, zb.value)}
+        v, tx, ty, zb, m = (ctypes.c_int32() for _ in range(5))
+        _check(lib().stencil_plan_config(self._h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(zb),
+                                         ctypes.byref(m)))
+        return {"variant": VARIANT_NAMES[v.value], "tile": (tx.value, ty.value, zb.value),
+                "tile_map": TILE_MAP_NAMES.get(m.value, m.value)}
 
     def profile(self, enable: bool = True):
         _check(lib().stencil_profile_enable(self._h, 1 if enable else 0))

@@ -1,0 +1,93 @@
+"""Exhaustive autotuner: the chosen launch shape is an offered one, results
+under it match the oracle, and the cache (in-process and JSON-lines file)
+returns the same choice without re-timing.
+
+The pick itself has no oracle: the exhaustive timing is the reference, and
+several shapes within timing noise are equally correct."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_13002_amd import synth
+from gpu_util import inner, maxrel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def test_tuned_heat3d7_matches_oracle_and_caches(dev):
+    from paper_2306_13002_amd.stencil import Plan
+    n = (61, 35, 47)
+    u0 = synth.heat3d7_input(*n, stream=11)
+    p = Plan("heat3d7", n, coef=(0.4, 0.1), tune="exhaustive")
+    cfg = p.config()
+    assert cfg["variant"] in ("plain", "saturated")
+    f = [torch.tensor(u0, device=dev), torch.full(u0.shape, float("nan"), dtype=torch.float64, device=dev)]
+    p.run(f, iterations=4)
+    got = f[0].cpu().numpy()
+    want, wr = oracle.heat(u0, 4, 0.4, 0.1)
+    assert maxrel(inner(got, 1), inner(want, 1)) <= 1e-12
+    assert abs(p.residual() - wr) <= 1e-10 * wr
+    p.close()
+    q = Plan("heat3d7", n, coef=(0.4, 0.1), tune="exhaustive")
+    assert q.config() == cfg
+    q.close()
+
+
+@pytest.mark.parametrize("variant", ["plain", "saturated"])
+def test_tuned_variant_restriction(dev, variant):
+    from paper_2306_13002_amd.stencil import Plan
+    n = (70, 19, 23)
+    p0, cf = synth.poisson19_random_inputs((n[2] + 2, n[1] + 2, n[0] + 2), seed=4)
+    p = Plan("poisson19", n, variant=variant, tune="exhaustive", omega=0.8)
+    assert p.config()["variant"] == variant
+    f = [torch.tensor(p0, device=dev), torch.zeros(p0.shape, dtype=torch.float32, device=dev)]
+    p.run(f, [torch.tensor(c, device=dev) for c in cf], iterations=3)
+    w64, _ = oracle.poisson19(p0, cf, 0.8, 3, mode="F64")
+    assert maxrel(inner(f[0].cpu().numpy(), 1), inner(w64, 1)) <= 1e-5
+    p.close()
+
+
+def test_tuned_partial_request_keeps_given_fields(dev):
+    from paper_2306_13002_amd.stencil import Plan
+    p = Plan("wave25", (40, 24, 30), variant="saturated", coef=synth.WAVE25_COEF, tune="exhaustive",
+             tile=(64, 0, 0))
+    cfg = p.config()
+    assert cfg["tile"][0] == 64 and cfg["variant"] == "saturated"
+    p.close()
+
+
+def test_tune_cache_file_roundtrip(tmp_path):
+    cache = tmp_path / "tune.jsonl"
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2306_13002_amd.stencil import Plan\n"
+            "p = Plan('heat3d7', (33, 29, 31), coef=(0.4, 0.1), tune='exhaustive')\n"
+            "print('CFG', p.config())\n") % ROOT
+    env = dict(os.environ, STENCIL_TUNE_CACHE=str(cache), STENCIL_LOG="1")
+    r1 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r1.returncode == 0, r1.stderr
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 1
+    e = json.loads(lines[0])
+    assert e["key"].startswith("k2/") and e["us"] > 0
+    assert "tune kind=2" in r1.stderr
+    r2 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r2.returncode == 0, r2.stderr
+    assert "tune kind=2" not in r2.stderr  # served from the file, not re-timed
+    cfg1 = [l for l in r1.stdout.splitlines() if l.startswith("CFG")]
+    cfg2 = [l for l in r2.stdout.splitlines() if l.startswith("CFG")]
+    assert cfg1 == cfg2
+    assert len(cache.read_text().strip().splitlines()) == 1
