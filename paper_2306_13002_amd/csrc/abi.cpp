@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -70,6 +71,7 @@ const KindOps *ops_for(int kind) {
     case STENCIL_HEAT3D7: return &heat3d7_ops;
     case STENCIL_POISSON19: return &poisson19_ops;
     case STENCIL_WAVE25: return &wave25_ops;
+    case STENCIL_GENERIC: return &generic_ops;
     default: return nullptr;
     }
 }
@@ -89,6 +91,67 @@ Tile default_tile(int kind, int variant, const Geom &g) {
 }
 
 int default_remap(int kind) { return kind == STENCIL_WAVE25 ? 0 : 1; }
+
+// GENERIC: build the plain and saturated tap tables and upload them.
+// Plain keeps the caller's order.  Saturated groups taps by (dz, coefficient
+// id), groups ordered by dz slot then id, taps in a group by address.
+stencil_status build_generic_tables(stencil_plan_s *p, const stencil_desc *d) {
+    const int n = d->n_taps, r = p->g.r, ns = 2 * r + 1;
+    std::vector<int> off(n), slot_g(ns + 1, 0), g_t, t_xy;
+    std::vector<double> c(n), g_c;
+    unsigned h = 2166136261u;
+    for (int t = 0; t < n; ++t) {
+        const int dx = d->tap_off[3 * t], dy = d->tap_off[3 * t + 1], dz = d->tap_off[3 * t + 2];
+        off[t] = (int)(dz * p->g.pz + dy * p->g.py + dx);
+        c[t] = d->coef[d->tap_cid[t]];
+        for (int v : {dx, dy, dz, d->tap_cid[t]}) h = (h ^ (unsigned)v) * 16777619u;
+    }
+    p->taps_hash = h;
+    for (int s = 0; s < ns; ++s) {
+        slot_g[s] = (int)g_c.size();
+        for (int id = 0; id < d->n_coef; ++id) {
+            std::vector<std::pair<int, int>> mem;  // (dy, dx)
+            for (int t = 0; t < n; ++t)
+                if (d->tap_off[3 * t + 2] == s - r && d->tap_cid[t] == id)
+                    mem.push_back({d->tap_off[3 * t + 1], d->tap_off[3 * t]});
+            if (mem.empty()) continue;
+            std::sort(mem.begin(), mem.end());
+            g_t.push_back((int)t_xy.size());
+            g_c.push_back(d->coef[id]);
+            for (auto &m : mem) t_xy.push_back((int)(((unsigned)m.first << 16) | ((unsigned)m.second & 0xFFFFu)));
+        }
+    }
+    slot_g[ns] = (int)g_c.size();
+    g_t.push_back((int)t_xy.size());
+    // one buffer: [off n][slot_g ns+1][g_t ng+1][t_xy n] (ints), then doubles [c n][g_c ng]
+    const size_t ni = off.size() + slot_g.size() + g_t.size() + t_xy.size();
+    const size_t ib = ((ni * sizeof(int)) + 15) & ~size_t(15);
+    const size_t total = ib + (c.size() + g_c.size()) * sizeof(double);
+    std::vector<char> host(total, 0);
+    int *ip = (int *)host.data();
+    size_t o = 0;
+    auto put = [&](const std::vector<int> &v) { std::memcpy(ip + o, v.data(), v.size() * sizeof(int)); size_t at = o; o += v.size(); return at; };
+    const size_t o_off = put(off), o_slot = put(slot_g), o_gt = put(g_t), o_xy = put(t_xy);
+    double *dp = (double *)(host.data() + ib);
+    std::memcpy(dp, c.data(), c.size() * sizeof(double));
+    std::memcpy(dp + c.size(), g_c.data(), g_c.size() * sizeof(double));
+    hipError_t e;
+    if ((e = hipMalloc(&p->d_tab, total)) != hipSuccess)
+        return fail(STENCIL_E_NOMEM, "hipMalloc tap tables: %s", hipGetErrorString(e));
+    if ((e = hipMemcpy(p->d_tab, host.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy tap tables");
+    const int *di = (const int *)p->d_tab;
+    const double *dd = (const double *)((const char *)p->d_tab + ib);
+    GenTab &t = p->base_args.gen;
+    t.off = di + o_off;
+    t.c = dd;
+    t.n = n;
+    t.slot_g = di + o_slot;
+    t.g_t = di + o_gt;
+    t.g_c = dd + c.size();
+    t.t_xy = di + o_xy;
+    return STENCIL_OK;
+}
 
 // Validate the descriptor (host only).  Fills geometry on success.
 stencil_status validate_desc(const stencil_desc *d, Geom &g, int &rz) {
@@ -192,6 +255,7 @@ void free_plan(stencil_plan_s *p) {
     if (p->device >= 0) (void)hipSetDevice(p->device);
     if (p->d_part) (void)hipFree(p->d_part);
     if (p->d_red) (void)hipFree(p->d_red);
+    if (p->d_tab) (void)hipFree(p->d_tab);
     if (p->d_result) (void)hipFree(p->d_result);
     if (p->h_result) (void)hipHostFree(p->h_result);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
@@ -262,7 +326,6 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out) {
     int rz = 0;
     stencil_status st = validate_desc(d, g, rz);
     if (st != STENCIL_OK) return st;
-    if (d->kind == STENCIL_GENERIC) return fail(STENCIL_E_UNSUPPORTED, "GENERIC stencils are not built into this library yet");
     if (d->tune == STENCIL_TUNE_MODEL)
         return fail(STENCIL_E_UNSUPPORTED, "tune mode MODEL is not available in this build");
     // device
@@ -282,9 +345,14 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out) {
     p->base_args.g = g;
     for (int c = 0; c < 5; ++c) p->base_args.c[c] = p->c[c];
     p->base_args.omega = d->omega;
+    p->base_args.elem_bytes = elem_bytes(d->dtype);
     if ((e = hipGetDevice(&p->device)) != hipSuccess) {
         delete p;
         return hip_fail(e, "hipGetDevice");
+    }
+    if (p->kind == STENCIL_GENERIC && (st = build_generic_tables(p, d)) != STENCIL_OK) {
+        free_plan(p);
+        return st;
     }
     if ((st = choose_config(p, d)) != STENCIL_OK || (st = alloc_plan_buffers(p)) != STENCIL_OK) {
         free_plan(p);

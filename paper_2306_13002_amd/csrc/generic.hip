@@ -1,0 +1,206 @@
+// generic.hip -- generic 3-D linear stencils (star or box, radius 1..4).
+//
+//   u'(x) = sum_t coef[cid_t] * u(x + delta_t)
+//
+// F32 or F64 storage; arithmetic is FP64 in both (operands widened on load,
+// the result rounded to the storage type on store).
+//
+// PLAIN: one thread per point; taps in the caller's order, each operand
+// loaded from memory, products rounded and added left to right.  The tap
+// table (linear offset, coefficient per tap) is uniform across the launch,
+// so it is read through the scalar cache.
+//
+// SATURATED: the paper's rewrites on the tap sum.  COMM/ASSOC gather the
+// taps that share a coefficient id AND a z offset into one group, summed
+// first (taps in ascending address order) and multiplied once with an FMA
+// (FMA1).  Loads: a block owns a TX x TY column tile and streams input
+// planes; each plane is staged once in LDS (with its r-wide ring, corners
+// included) and contributes to the 2r+1 output planes it touches, which
+// wait in a register queue of FP64 accumulators (plane accumulation), so
+// every input value is read from memory once per block.  The next plane's
+// loads are issued before the current plane's arithmetic.
+#include "internal.hpp"
+
+namespace stn {
+namespace {
+
+constexpr int kMaxWaves = 16;
+
+template <typename T>
+__global__ void generic_plain(const T *__restrict__ src, T *__restrict__ dst, Geom g, GenTab tab,
+                             double *__restrict__ part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    double d2 = 0.0;
+    if (i < g.nx && j < g.ny && k < g.nz) {
+        const long long q = (long long)(k + g.r) * g.pz + (long long)(j + g.r) * g.py + (i + g.r);
+        double v = tab.c[0] * (double)src[q + tab.off[0]];
+        for (int t = 1; t < tab.n; ++t) v = v + tab.c[t] * (double)src[q + tab.off[t]];
+        const T out = (T)v;
+        dst[q] = out;
+        const double d = (double)out - (double)src[q];
+        d2 = d * d;
+    }
+    if (part) {
+        __shared__ double lds[kMaxWaves];
+        const double s = block_sum_f64(d2, lds);
+        if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) part[block_linear_id()] = s;
+    }
+}
+
+template <typename T, int R, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void generic_sat(const T *__restrict__ src, T *__restrict__ dst, Geom g,
+                                                      GenTab tab, int zb, int remap, double *__restrict__ part) {
+    constexpr int W = TX + 2 * R, NT = TX * TY, PLANE = (TY + 2 * R) * W, NQ = 2 * R + 1;
+    __shared__ double tile[2][PLANE];
+    __shared__ double red[kMaxWaves];
+    int bx, by, bz;
+    tile_coords(remap, bx, by, bz);
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+    const int i = bx * TX + tx, j = by * TY + ty;
+    const int xp = i + R, yp = j + R;
+    const int PX = g.nx + 2 * R, PY = g.ny + 2 * R;
+    const bool in = i < g.nx && j < g.ny;
+    const bool ld = xp < PX && yp < PY;
+    const int k0 = bz * zb, k1 = min(k0 + zb, g.nz);
+    const long long col = (long long)yp * g.py + xp;
+    const int me = (ty + R) * W + (tx + R);
+
+    HaloStager<T, TX, TY, R, true, NT> halo;
+    halo.init(tid, bx * TX + R, by * TY + R, g.py, PX, PY);
+
+    // acc[s]: output plane m + R - s after input plane m; ctr[s]: that
+    // output's old value (for the residual)
+    double acc[NQ], ctr[NQ];
+#pragma unroll
+    for (int s = 0; s < NQ; ++s) {
+        acc[s] = 0.0;
+        ctr[s] = 0.0;
+    }
+    // input planes m = k0-R .. k1-1+R  (padded z = m + R)
+    int zp = k0;
+    T cval = ld ? src[col + (long long)zp * g.pz] : T(0);
+    halo.load(src + (long long)zp * g.pz);
+    double sacc = 0.0;
+    const int zend = k1 - 1 + 2 * R;
+    for (int b = 0; zp <= zend; ++zp, b ^= 1) {
+        double *t = tile[b];
+        t[me] = (double)cval;
+#pragma unroll
+        for (int s = 0; s < decltype(halo)::HR; ++s)
+            if (halo.has[s]) t[halo.lidx[s]] = (double)halo.val[s];
+        const double cur_ctr = (double)cval;
+        if (zp < zend) {  // bulk load of the next plane
+            cval = ld ? src[col + (long long)(zp + 1) * g.pz] : T(0);
+            halo.load(src + (long long)(zp + 1) * g.pz);
+        }
+        __syncthreads();
+        // shift the queues (input plane m = zp - R): slot s now holds output
+        // plane m + R - s, slot 0 starts empty
+#pragma unroll
+        for (int s = NQ - 1; s > 0; --s) {
+            acc[s] = acc[s - 1];
+            ctr[s] = ctr[s - 1];
+        }
+        acc[0] = 0.0;
+        ctr[0] = 0.0;
+        // the centre value of this input plane is the old value of output m,
+        // which sits in slot R after the shift
+        ctr[R] = cur_ctr;
+#pragma unroll
+        for (int s = 0; s < NQ; ++s) {
+            // slot s receives taps with dz = s - R
+            const int g0 = tab.slot_g[s], g1 = tab.slot_g[s + 1];
+            double a = acc[s];
+            for (int gi = g0; gi < g1; ++gi) {
+                const int t0 = tab.g_t[gi], t1 = tab.g_t[gi + 1];
+                double sum = 0.0;
+                for (int ti = t0; ti < t1; ++ti) {
+                    const int xy = tab.t_xy[ti];
+                    const int dx = (short)(xy & 0xFFFF), dy = xy >> 16;
+                    sum += t[me + dy * W + dx];
+                }
+                a = fma(tab.g_c[gi], sum, a);
+            }
+            acc[s] = a;
+        }
+        // output m - R (slot 2R) is complete
+        const int kout = zp - 2 * R;  // interior index of output m - R (m = zp - R)
+        if (in && kout >= k0 && kout < k1) {
+            const T out = (T)acc[2 * R];
+            dst[col + (long long)(kout + R) * g.pz] = out;
+            const double d = (double)out - ctr[2 * R];
+            sacc = fma(d, d, sacc);
+        }
+    }
+    if (part) {
+        const double s = block_sum_f64(sacc, red);
+        if (tid == 0) part[block_linear_id()] = s;
+    }
+}
+
+bool plain_tile_ok(Tile t) {
+    const long long n = (long long)t.tx * t.ty * t.tz;
+    return t.tx >= 1 && t.ty >= 1 && t.tz >= 1 && n % 64 == 0 && n <= 1024;
+}
+
+#define GEN_SAT_TILES(X) X(32, 2) X(32, 4) X(32, 8) X(64, 1) X(64, 2) X(64, 4) X(128, 1) X(128, 2)
+
+bool gen_tile_ok(int v, Tile t) {
+    if (v == V_PLAIN) return plain_tile_ok(t);
+    if (t.tz < 1) return false;
+#define X(a, b) if (t.tx == a && t.ty == b) return true;
+    GEN_SAT_TILES(X)
+#undef X
+    return false;
+}
+
+int gen_sat_tiles(Tile *out, int max) {
+    int n = 0;
+#define X(a, b) if (n < max) out[n++] = Tile{a, b, 0};
+    GEN_SAT_TILES(X)
+#undef X
+    return n;
+}
+
+long long gen_nblocks(int, Tile t, const Geom &g) { return cdiv(g.nx, t.tx) * cdiv(g.ny, t.ty) * cdiv(g.nz, t.tz); }
+
+template <typename T>
+hipError_t gen_launch_t(int v, Tile t, const SweepArgs &a, hipStream_t s) {
+    const T *src = (const T *)a.src;
+    T *dst = (T *)a.dst;
+    dim3 grid(cdiv(a.g.nx, t.tx), cdiv(a.g.ny, t.ty), cdiv(a.g.nz, t.tz));
+    if (v == V_PLAIN) {
+        hipLaunchKernelGGL(generic_plain<T>, grid, dim3(t.tx, t.ty, t.tz), 0, s, src, dst, a.g, a.gen, a.part);
+        return hipGetLastError();
+    }
+#define X(A, B)                                                                                             \
+    if (t.tx == A && t.ty == B) {                                                                           \
+        switch (a.g.r) {                                                                                    \
+        case 1: hipLaunchKernelGGL((generic_sat<T, 1, A, B>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.gen, \
+                                   t.tz, a.remap, a.part); break;                                           \
+        case 2: hipLaunchKernelGGL((generic_sat<T, 2, A, B>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.gen, \
+                                   t.tz, a.remap, a.part); break;                                           \
+        case 3: hipLaunchKernelGGL((generic_sat<T, 3, A, B>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.gen, \
+                                   t.tz, a.remap, a.part); break;                                           \
+        case 4: hipLaunchKernelGGL((generic_sat<T, 4, A, B>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.gen, \
+                                   t.tz, a.remap, a.part); break;                                           \
+        default: return hipErrorInvalidValue;                                                               \
+        }                                                                                                   \
+        return hipGetLastError();                                                                           \
+    }
+    GEN_SAT_TILES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t gen_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
+    return a.elem_bytes == 4 ? gen_launch_t<float>(v, t, a, s) : gen_launch_t<double>(v, t, a, s);
+}
+
+}  // namespace
+
+KindOps generic_ops = {gen_tile_ok, gen_sat_tiles, gen_nblocks, gen_launch};
+
+}  // namespace stn

@@ -46,11 +46,13 @@ __global__ void heat2d5_plain(const double *__restrict__ src, double *__restrict
     }
 }
 
-__global__ void heat3d7_plain(const double *__restrict__ src, double *__restrict__ dst, Geom g, double cc,
-                              double cn, double *__restrict__ part) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+// Plain 3-D body for one block-shaped tile (bx, by, bz) of blockDim points;
+// returns this thread's squared change.
+__device__ __forceinline__ double heat3d7_plain_tile(const double *__restrict__ src, double *__restrict__ dst,
+                                                     const Geom &g, double cc, double cn, int bx, int by, int bz) {
+    const int i = bx * blockDim.x + threadIdx.x;
+    const int j = by * blockDim.y + threadIdx.y;
+    const int k = bz * blockDim.z + threadIdx.z;
     double d2 = 0.0;
     if (i < g.nx && j < g.ny && k < g.nz) {
         const long long q = (long long)(k + 1) * g.pz + (long long)(j + 1) * g.py + (i + 1);
@@ -66,6 +68,12 @@ __global__ void heat3d7_plain(const double *__restrict__ src, double *__restrict
         const double d = v - u;
         d2 = d * d;
     }
+    return d2;
+}
+
+__global__ void heat3d7_plain(const double *__restrict__ src, double *__restrict__ dst, Geom g, double cc,
+                              double cn, double *__restrict__ part) {
+    const double d2 = heat3d7_plain_tile(src, dst, g, cc, cn, blockIdx.x, blockIdx.y, blockIdx.z);
     if (part) {
         __shared__ double lds[kMaxWaves];
         const double s = block_sum_f64(d2, lds);
@@ -73,17 +81,15 @@ __global__ void heat3d7_plain(const double *__restrict__ src, double *__restrict
     }
 }
 
-// Saturated 3-D sweep.  Block (TX, TY) threads, one column each; grid
-// (ceil(nx/TX), ceil(ny/TY), ceil(nz/zb)).
+// Saturated 3-D body for one TX x TY column tile (bx, by) streaming planes
+// [bz*zb, bz*zb + zb); block (TX, TY) threads, one column each.  Returns this
+// thread's sum of squared changes.  Ends with every LDS read done before the
+// caller's next barrier-protected use of `tile`.
 template <int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void heat3d7_sat(const double *__restrict__ src, double *__restrict__ dst,
-                                                      Geom g, double cc, double cn, int zb, int remap,
-                                                      double *__restrict__ part) {
+__device__ __forceinline__ double heat3d7_sat_tile(const double *__restrict__ src, double *__restrict__ dst,
+                                                   const Geom &g, double cc, double cn, int zb, int bx, int by,
+                                                   int bz, double (*tile)[(TY + 2) * (TX + 2)]) {
     constexpr int R = 1, W = TX + 2 * R, NT = TX * TY;
-    __shared__ double tile[2][(TY + 2 * R) * W];
-    __shared__ double red[kMaxWaves];
-    int bx, by, bz;
-    tile_coords(remap, bx, by, bz);
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const int i = bx * TX + tx, j = by * TY + ty;
     const int xp = i + R, yp = j + R;
@@ -126,9 +132,21 @@ __global__ __launch_bounds__(TX *TY) void heat3d7_sat(const double *__restrict__
         cur = nxt;
         nxt = nn;
     }
+    return acc;
+}
+
+template <int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void heat3d7_sat(const double *__restrict__ src, double *__restrict__ dst,
+                                                      Geom g, double cc, double cn, int zb, int remap,
+                                                      double *__restrict__ part) {
+    __shared__ double tile[2][(TY + 2) * (TX + 2)];
+    __shared__ double red[kMaxWaves];
+    int bx, by, bz;
+    tile_coords(remap, bx, by, bz);
+    const double acc = heat3d7_sat_tile<TX, TY>(src, dst, g, cc, cn, zb, bx, by, bz, tile);
     if (part) {
         const double s = block_sum_f64(acc, red);
-        if (tid == 0) part[block_linear_id()] = s;
+        if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = s;
     }
 }
 

@@ -16,6 +16,17 @@ struct Tile {
     int tx, ty, tz;
 };
 
+// GENERIC tap tables (device pointers, uniform over a launch).
+struct GenTab {
+    const int *off;     // plain: linear offset dz*pz + dy*py + dx per tap, caller's order
+    const double *c;    // plain: coefficient per tap
+    int n;              // number of taps
+    const int *slot_g;  // saturated: groups of z-offset slot s (dz = s - r) are [slot_g[s], slot_g[s+1])
+    const int *g_t;     // saturated: taps of group g are [g_t[g], g_t[g+1])
+    const double *g_c;  // saturated: coefficient of group g
+    const int *t_xy;    // saturated: (dy << 16) | (dx & 0xffff) per tap, ascending address in a group
+};
+
 // Arguments of one sweep launch.
 struct SweepArgs {
     const void *src;          // Jacobi kinds: state read; WAVE25: u^n
@@ -29,6 +40,8 @@ struct SweepArgs {
     const double *tap_coef;   // GENERIC: device coefficient table
     int n_taps, n_coef;
     int remap;                // saturated forms: XCD-chunked block -> tile map (1) or natural order (0)
+    GenTab gen;               // GENERIC tap tables
+    int elem_bytes;           // storage size (GENERIC: 4 or 8)
 };
 
 struct KindOps {
@@ -38,7 +51,7 @@ struct KindOps {
     hipError_t (*launch)(int variant, Tile t, const SweepArgs &a, hipStream_t s);
 };
 
-extern KindOps heat2d5_ops, heat3d7_ops, poisson19_ops, wave25_ops;
+extern KindOps heat2d5_ops, heat3d7_ops, poisson19_ops, wave25_ops, generic_ops;
 
 // Support kernels (support.hip).
 hipError_t launch_halo_copy(const void *src, void *dst, int elem_bytes, const Geom &g, int rz, hipStream_t s);

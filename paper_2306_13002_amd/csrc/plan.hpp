@@ -28,5 +28,6 @@ struct stencil_plan_s {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     stn::SweepArgs base_args{};  // geometry and scalars shared by every launch of this plan
     unsigned taps_hash = 0;      // GENERIC: hash of the tap pattern (part of the tune key)
+    void *d_tab = nullptr;       // GENERIC: device tap tables
     bool tuned = false;          // configuration came from the autotuner
 };

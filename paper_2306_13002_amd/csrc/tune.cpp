@@ -186,7 +186,7 @@ stencil_status tune_exhaustive(stencil_plan_s *p, const TuneRequest &rq, TuneEnt
     hipError_t e;
     for (int i = 0; i < 2; ++i)
         if ((e = hipMalloc(&b.f[i], bytes)) != hipSuccess) return fail(STENCIL_E_NOMEM, "tuner buffers: %s", hipGetErrorString(e));
-    b.nc = p->kind == STENCIL_POISSON19 ? 12 : (p->kind == STENCIL_WAVE25 ? 1 : 0);
+    b.nc = p->kind == STENCIL_POISSON19 ? 12 : (p->kind == STENCIL_WAVE25 ? 1 : 0);  // GENERIC: none
     const size_t cb = p->kind == STENCIL_POISSON19 ? (size_t)span * 4 : bytes;
     for (int i = 0; i < b.nc; ++i)
         if ((e = hipMalloc(&b.c[i], cb)) != hipSuccess) return fail(STENCIL_E_NOMEM, "tuner buffers: %s", hipGetErrorString(e));

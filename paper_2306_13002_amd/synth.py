@@ -177,3 +177,80 @@ def wave25_inputs(nx: int, ny: int | None = None, nz: int | None = None, seed: i
     del v
     u = 1.0 + 0.1 * uniform_f64(seed, 1, shape)
     return u, u.copy(), vsq
+
+
+# --------------------------------------------------------------------------
+# generic stencils: seeded random corpus (star or box, radius 1..4)
+GENERIC_CORPUS = dict(count=250, train=200, seed=5, edge_lo=64, edge_hi=512, T=4)
+SHARING = ("distinct", "reflection", "symmetric", "partition")
+
+
+def star_taps(r: int):
+    """Centre, then for x, y, z: +q, -q for q = 1..r."""
+    taps = [(0, 0, 0)]
+    for ax in range(3):
+        for q in range(1, r + 1):
+            for s in (q, -q):
+                d = [0, 0, 0]
+                d[ax] = s
+                taps.append(tuple(d))
+    return taps
+
+
+def box_taps(r: int):
+    """All (dx, dy, dz) in [-r, r]^3, dz slowest, dx fastest."""
+    return [(dx, dy, dz) for dz in range(-r, r + 1) for dy in range(-r, r + 1) for dx in range(-r, r + 1)]
+
+
+def sharing_ids(taps, pattern: str, u_iter):
+    """Coefficient id per tap for a sharing pattern (ids are dense 0..m-1)."""
+    if pattern == "distinct":
+        return list(range(len(taps))), len(taps)
+    if pattern in ("reflection", "symmetric"):
+        keys = {}
+        ids = []
+        for d in taps:
+            if pattern == "reflection":
+                k = max(d, tuple(-v for v in d))
+            else:
+                k = tuple(sorted(abs(v) for v in d))
+            ids.append(keys.setdefault(k, len(keys)))
+        return ids, len(keys)
+    m = 1 + int(next(u_iter) * len(taps))
+    m = min(m, len(taps))
+    ids = [min(m - 1, int(next(u_iter) * m)) for _ in taps]
+    used = sorted(set(ids))
+    remap = {v: i for i, v in enumerate(used)}
+    return [remap[v] for v in ids], len(used)
+
+
+def generic_stencil(index: int, seed: int = 5, max_edge: int | None = None):
+    """Stencil number `index` of the seeded corpus: a dict with radius, shape,
+    dtype, interior n (x, y, z), taps, cids, coef.  Every draw comes from
+    stream `index`: radius 1 + floor(4u); box if u < 0.5; F32 if u < 0.5;
+    each edge 64 + floor(449u); sharing pattern floor(4u); coefficient values
+    U(0.1, 1) per id, normalized so the taps' coefficients sum to 1.
+    max_edge caps the grid (parity runs use a shrunken grid)."""
+    u = iter(uniform_f64(seed, index, (4096,)))
+    r = 1 + int(next(u) * 4)
+    box = next(u) < 0.5
+    dtype = "f32" if next(u) < 0.5 else "f64"
+    n = [64 + int(next(u) * 449) for _ in range(3)]
+    pattern = SHARING[int(next(u) * 4)]
+    taps = box_taps(r) if box else star_taps(r)
+    cids, m = sharing_ids(taps, pattern, u)
+    vals = [0.1 + 0.9 * next(u) for _ in range(m)]
+    total = sum(vals[c] for c in cids)
+    coef = [v / total for v in vals]
+    if max_edge is not None:
+        n = [min(e, max_edge) for e in n]
+    return dict(index=index, radius=r, shape="box" if box else "star", dtype=dtype, n=tuple(n),
+                pattern=pattern, taps=taps, cids=cids, coef=coef)
+
+
+def generic_input(n, r: int, dtype: str, seed: int = 5, stream: int = 1000):
+    """U[0,1) padded grid (halo included) for a generic stencil."""
+    shape = (n[2] + 2 * r, n[1] + 2 * r, n[0] + 2 * r)
+    if dtype == "f32":
+        return uniform_f32(seed, stream, shape)
+    return uniform_f64(seed, stream, shape)
