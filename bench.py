@@ -121,6 +121,54 @@ def setup_workload(name, variant, dev, torch, synth, Plan):
                     iterations=T, bytes_per_update=16, kernel_tag=f"{name}_{variant}", source="heat.hip",
                     storage="f64")
         return plan, step, reset, pts * T, T, meta
+    if name == "batch":
+        from paper_2306_13002_amd.stencil import BatchPlan
+        sizes = synth.heat3d7_batch_sizes()
+        T = 50
+        us = [synth.heat3d7_input(*n, stream=1 + b) for b, n in enumerate(sizes)]
+        fs = [(torch.tensor(u, device=dev), torch.empty(u.shape, dtype=torch.float64, device=dev)) for u in us]
+        pts = sum(n[0] * n[1] * n[2] for n in sizes)
+        if variant == "saturated":  # the batched graph, classes tuned
+            plan = BatchPlan(sizes, tune=TUNE)
+
+            def step():
+                plan.run(fs, iterations=T)
+                return plan.residual()
+        else:  # baseline: 64 separate plain runs at the default launch shape
+            plans = [Plan("heat3d7", n, variant="plain", coef=(0.4, 0.1)) for n in sizes]
+
+            class _Seq:
+                def profile(self, on):
+                    self.ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+                def profile_read(self):
+                    self.ev[1].synchronize()
+                    return self.ev[0].elapsed_time(self.ev[1]), T
+
+                def config(self):
+                    return plans[0].config()
+
+                def close(self):
+                    for q in plans:
+                        q.close()
+
+            plan = _Seq()
+
+            def step():
+                plan.ev[0].record()
+                for q, f in zip(plans, fs):
+                    q.run(list(f), iterations=T)
+                plan.ev[1].record()
+                return sum(q.residual() for q in plans)
+
+        class _BatchCfg:
+            pass
+
+        meta = dict(workload="64 independent heat3d7 FP64 grids, edges 32..160 (seeded), 50 sweeps each + "
+                             "residuals; batched graph vs 64 separate plain runs",
+                    interior=[len(sizes), pts], iterations=T, bytes_per_update=16, kernel_tag="heat3d7_batch",
+                    source="heat.hip", storage="f64")
+        return plan, step, (lambda: None), pts * T, T, meta
     if name == "copy":
         # plain device-to-device copy of 1 GiB: the streaming ceiling, and the
         # known-size kernel that calibrates the HBM byte counters
@@ -228,7 +276,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="poisson19", choices=["poisson19", "wave25", "heat2d5", "heat3d7", "copy"])
+    ap.add_argument("--workload", default="poisson19", choices=["poisson19", "wave25", "heat2d5", "heat3d7", "batch", "copy"])
     ap.add_argument("--variant", default="saturated", choices=["saturated", "plain"])
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain form beside it")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -299,7 +347,7 @@ def main():
                         "achieved_gbs": alg_bytes / pl / 1e9, "avg_launch_us": pl * 1e6,
                         "tile": list(pr["cfg"]["tile"]), "tile_map": pr["cfg"].get("tile_map")}
         out["saturated_over_plain"] = value / pv
-    if not a.no_cpu and a.workload != "copy":
+    if not a.no_cpu and a.workload not in ("copy", "batch"):
         out["cpu_baseline"] = cpu_baseline(a.workload)
     print(json.dumps(out), flush=True)
 

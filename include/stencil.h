@@ -131,6 +131,18 @@ typedef struct {
  * On success *out is a new plan; on error *out = NULL. */
 stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out);
 
+/* Build one plan over `count` independent grids (HEAT3D7, Dirichlet), run
+ * together: problems are grouped into size classes by their largest
+ * interior edge (<= 64, then buckets of 32); each class gets one form and
+ * launch shape -- from the autotuner on the class's largest problem when
+ * ds[0].tune is EXHAUSTIVE, else the defaults or ds[0]'s fields -- and a
+ * persistent work-list kernel over (problem, tile) items.  stencil_run on a
+ * batch plan takes fields = {p0.fields[0], p0.fields[1], p1.fields[0], ...}
+ * and replays one hipGraph per (iterations, field pointers): halo copies, the
+ * class chains as parallel branches, tail copies.  Each problem's result is
+ * bit-identical to its own single plan with the same form and shape. */
+stencil_status stencil_plan_batch(const stencil_desc *ds, int32_t count, stencil_plan_t *out);
+
 /* Run `iterations` sweeps asynchronously on `stream`.
  * fields (device pointers):
  *   HEAT*, GENERIC, POISSON19: fields[0] = state (in/out), fields[1] = a
@@ -153,6 +165,11 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
  * a fixed order (bitwise reproducible), copies 8 bytes to the host and
  * synchronizes `stream`.  E_STATE if no sweep has run on this plan. */
 stencil_status stencil_residual(stencil_plan_t p, double *host_out, void *stream);
+
+/* Per-problem residuals of the last run of a batch plan (count = number of
+ * problems; a single plan takes count = 1).  stencil_residual on a batch
+ * plan returns their sum in problem order.  Synchronizes `stream`. */
+stencil_status stencil_residuals(stencil_plan_t p, double *host_out, int32_t count, void *stream);
 
 /* Chosen configuration of a plan (any output pointer may be NULL).
  * tile_map is reported as 1 (natural) or 2 (XCD-chunked). */

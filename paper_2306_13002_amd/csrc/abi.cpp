@@ -248,6 +248,10 @@ stencil_status alloc_plan_buffers(stencil_plan_s *p) {
     return STENCIL_OK;
 }
 
+void free_batch(BatchState *b);
+stencil_status batch_run(stencil_plan_s *p, void *const *fields, int T, hipStream_t s);
+stencil_status batch_residuals(stencil_plan_s *p, double *out, int count, hipStream_t s);
+
 void free_plan(stencil_plan_s *p) {
     if (!p) return;
     int cur = -1;
@@ -256,6 +260,7 @@ void free_plan(stencil_plan_s *p) {
     if (p->d_part) (void)hipFree(p->d_part);
     if (p->d_red) (void)hipFree(p->d_red);
     if (p->d_tab) (void)hipFree(p->d_tab);
+    free_batch(p->batch);
     if (p->d_result) (void)hipFree(p->d_result);
     if (p->h_result) (void)hipHostFree(p->h_result);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
@@ -367,7 +372,14 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out) {
 stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *const *coef_arrays, int32_t iterations,
                            void *stream_) {
     if (!p) return fail(STENCIL_E_INVAL, "plan is NULL");
-    if (!fields || !fields[0] || !fields[1]) return fail(STENCIL_E_INVAL, "fields[0] and fields[1] are required");
+    if (!fields) return fail(STENCIL_E_INVAL, "fields is NULL");
+    if (iterations < 0) return fail(STENCIL_E_INVAL, "iterations < 0");
+    if (p->batch) {
+        DeviceGuard guard(p->device);
+        if (!guard.ok) return fail(STENCIL_E_DEVICE, "cannot make device %d current", p->device);
+        return batch_run(p, fields, iterations, (hipStream_t)stream_);
+    }
+    if (!fields[0] || !fields[1]) return fail(STENCIL_E_INVAL, "fields[0] and fields[1] are required");
     if (fields[0] == fields[1]) return fail(STENCIL_E_INVAL, "fields[0] and fields[1] must be distinct");
     if (iterations < 0) return fail(STENCIL_E_INVAL, "iterations < 0");
     const int eb = elem_bytes(p->dtype);
@@ -432,6 +444,7 @@ stencil_status stencil_residual(stencil_plan_t p, double *host_out, void *stream
     DeviceGuard guard(p->device);
     if (!guard.ok) return fail(STENCIL_E_DEVICE, "cannot make device %d current", p->device);
     hipStream_t s = (hipStream_t)stream_;
+    if (p->batch) return batch_residuals(p, host_out, 1, s);
     hipError_t e;
     if ((e = launch_reduce_partials(p->d_part, p->nblocks, p->d_red, p->d_result, s)) != hipSuccess)
         return hip_fail(e, "reduce launch");
@@ -440,6 +453,17 @@ stencil_status stencil_residual(stencil_plan_t p, double *host_out, void *stream
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     *host_out = *p->h_result;
     return STENCIL_OK;
+}
+
+stencil_status stencil_residuals(stencil_plan_t p, double *host_out, int32_t count, void *stream_) {
+    if (!p || !host_out) return fail(STENCIL_E_INVAL, "plan and host_out are required");
+    const int n = p->batch ? p->batch->count : 1;
+    if (count != n) return fail(STENCIL_E_INVAL, "count %d != number of problems %d", count, n);
+    if (!p->batch) return stencil_residual(p, host_out, stream_);
+    if (!p->has_resid) return fail(STENCIL_E_STATE, "no sweep has run on this plan");
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return fail(STENCIL_E_DEVICE, "cannot make device %d current", p->device);
+    return batch_residuals(p, host_out, count, (hipStream_t)stream_);
 }
 
 stencil_status stencil_plan_config(stencil_plan_t p, int32_t *variant, int32_t *tile_x, int32_t *tile_y,

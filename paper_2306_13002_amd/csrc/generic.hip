@@ -201,6 +201,6 @@ hipError_t gen_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 
 }  // namespace
 
-KindOps generic_ops = {gen_tile_ok, gen_sat_tiles, gen_nblocks, gen_launch};
+KindOps generic_ops = {gen_tile_ok, gen_sat_tiles, gen_nblocks, gen_launch, nullptr};
 
 }  // namespace stn

@@ -150,6 +150,43 @@ __global__ __launch_bounds__(TX *TY) void heat3d7_sat(const double *__restrict__
     }
 }
 
+// Persistent work-list forms: each block walks items blockIdx.x, +gridDim.x,
+// ... and runs the same tile body as the single-problem kernel, so a batched
+// problem is bit-identical to its own run with the same form and shape.
+template <int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void heat3d7_sat_batch(const BatchProb *__restrict__ probs,
+                                                            const BatchItem *__restrict__ items, int n_items,
+                                                            int parity, int zb, double *__restrict__ part) {
+    __shared__ double tile[2][(TY + 2) * (TX + 2)];
+    __shared__ double red[kMaxWaves];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const BatchItem w = items[it];
+        const BatchProb &P = probs[w.prob];
+        const double acc = heat3d7_sat_tile<TX, TY>(P.f[parity], P.f[parity ^ 1], P.g, P.cc, P.cn, zb, w.bx, w.by,
+                                                    w.bz, tile);
+        if (part) {
+            const double s = block_sum_f64(acc, red);
+            if (threadIdx.x == 0 && threadIdx.y == 0) part[it] = s;
+        }
+        __syncthreads();  // LDS is reused by the next item
+    }
+}
+
+__global__ void heat3d7_plain_batch(const BatchProb *__restrict__ probs, const BatchItem *__restrict__ items,
+                                    int n_items, int parity, double *__restrict__ part) {
+    __shared__ double red[kMaxWaves];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const BatchItem w = items[it];
+        const BatchProb &P = probs[w.prob];
+        const double d2 = heat3d7_plain_tile(P.f[parity], P.f[parity ^ 1], P.g, P.cc, P.cn, w.bx, w.by, w.bz);
+        if (part) {
+            const double s = block_sum_f64(d2, red);
+            if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) part[it] = s;
+        }
+        __syncthreads();
+    }
+}
+
 // ----------------------------------------------------------------------------
 bool plain_tile_ok(Tile t) {
     const long long n = (long long)t.tx * t.ty * t.tz;
@@ -213,9 +250,27 @@ hipError_t h3_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+hipError_t h3_batch_launch(int v, Tile t, const BatchProb *probs, const BatchItem *items, int n_items, int parity,
+                           int grid, double *part, hipStream_t s) {
+    if (v == V_PLAIN) {
+        hipLaunchKernelGGL(heat3d7_plain_batch, dim3(grid), dim3(t.tx, t.ty, t.tz), 0, s, probs, items, n_items, parity,
+                           part);
+        return hipGetLastError();
+    }
+#define X(A, B)                                                                                                \
+    if (t.tx == A && t.ty == B) {                                                                              \
+        hipLaunchKernelGGL((heat3d7_sat_batch<A, B>), dim3(grid), dim3(A, B, 1), 0, s, probs, items, n_items,   \
+                           parity, t.tz, part);                                                                \
+        return hipGetLastError();                                                                              \
+    }
+    HEAT3D7_SAT_TILES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
 
-KindOps heat2d5_ops = {h2_tile_ok, nullptr, h2_nblocks, h2_launch};
-KindOps heat3d7_ops = {h3_tile_ok, h3_sat_tiles, h3_nblocks, h3_launch};
+KindOps heat2d5_ops = {h2_tile_ok, nullptr, h2_nblocks, h2_launch, nullptr};
+KindOps heat3d7_ops = {h3_tile_ok, h3_sat_tiles, h3_nblocks, h3_launch, h3_batch_launch};
 
 }  // namespace stn

@@ -44,11 +44,27 @@ struct SweepArgs {
     int elem_bytes;           // storage size (GENERIC: 4 or 8)
 };
 
+// Batched runs: one problem of a batch and one work item (a tile of a
+// problem in its class's launch shape).
+struct BatchProb {
+    double *f[2];  // the problem's fields[0], fields[1]
+    Geom g;
+    double cc, cn;
+};
+struct BatchItem {
+    int prob, bx, by, bz;
+};
+
 struct KindOps {
     bool (*tile_ok)(int variant, Tile t);
     int (*sat_tiles)(Tile *out, int max);  // offered saturated (tx, ty) shapes; nullptr if none
     long long (*nblocks)(int variant, Tile t, const Geom &g);
     hipError_t (*launch)(int variant, Tile t, const SweepArgs &a, hipStream_t s);
+    // Persistent work-list sweep over a batch (nullptr: kind not batchable).
+    // Items [0, n_items) are visited by `grid` blocks in a fixed stride; the
+    // residual partial of item i goes to part[i] when part is non-null.
+    hipError_t (*batch_launch)(int variant, Tile t, const BatchProb *probs, const BatchItem *items, int n_items,
+                               int parity, int grid, double *part, hipStream_t s);
 };
 
 extern KindOps heat2d5_ops, heat3d7_ops, poisson19_ops, wave25_ops, generic_ops;
@@ -62,6 +78,8 @@ hipError_t launch_interior_copy(const void *src, void *dst, int elem_bytes, cons
 // chunk of part[] into scratch[], then one block sums scratch[].
 constexpr int kReduceBlocks = 256;
 hipError_t launch_reduce_partials(const double *part, long long n, double *scratch, double *out, hipStream_t s);
+// out[p] = sum of part[seg[p] .. seg[count+p]) in a fixed order, p < count.
+hipError_t launch_segment_sums(const double *part, const int *seg, int count, double *out, hipStream_t s);
 
 inline long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 

@@ -6,6 +6,33 @@
 #include "../../include/stencil.h"
 #include "internal.hpp"
 
+#include <vector>
+
+// Batched plan state (see batch.cpp).
+struct BatchClass {
+    int variant = 0;
+    stn::Tile tile{};
+    int n_items = 0, item_base = 0, grid = 0;
+};
+struct BatchState {
+    int count = 0, n_items = 0;
+    std::vector<stn::BatchProb> probs;  // host copy of the problem table
+    std::vector<BatchClass> classes;
+    stn::BatchItem *d_items = nullptr;  // class-major, then problem, then tile (x fastest)
+    stn::BatchProb *d_probs = nullptr;
+    int *d_seg = nullptr;               // per problem: item begin [count], item end [count]
+    double *d_part = nullptr;           // residual partial per item
+    double *d_res = nullptr;            // residual per problem
+    double *h_res = nullptr;            // pinned copy
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_T = -1;
+    std::vector<void *> graph_fields;
+    hipStream_t cap = nullptr;          // capture stream
+    std::vector<hipStream_t> side;      // one per class (graph branches)
+    std::vector<hipEvent_t> evs;        // fork + one join per class
+};
+
 struct stencil_plan_s {
     int kind = 0, dtype = 0, bc = 0;
     int variant = 0;            // resolved: stn::V_PLAIN or stn::V_SATURATED
@@ -30,4 +57,5 @@ struct stencil_plan_s {
     unsigned taps_hash = 0;      // GENERIC: hash of the tap pattern (part of the tune key)
     void *d_tab = nullptr;       // GENERIC: device tap tables
     bool tuned = false;          // configuration came from the autotuner
+    BatchState *batch = nullptr; // non-null for plans made by stencil_plan_batch
 };

@@ -214,6 +214,6 @@ hipError_t p19_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 
 }  // namespace
 
-KindOps poisson19_ops = {p19_tile_ok, p19_sat_tiles, p19_nblocks, p19_launch};
+KindOps poisson19_ops = {p19_tile_ok, p19_sat_tiles, p19_nblocks, p19_launch, nullptr};
 
 }  // namespace stn

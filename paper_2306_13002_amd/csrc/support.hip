@@ -97,6 +97,17 @@ __global__ void fill_kernel(T *__restrict__ buf, long long n, T v) {
         buf[t] = v;
 }
 
+// seg holds count begins, then count ends.
+__global__ void segment_sums_kernel(const double *__restrict__ part, const int *__restrict__ seg, int count,
+                                    double *__restrict__ out) {
+    __shared__ double lds[4];
+    const int b0 = seg[blockIdx.x], b1 = seg[count + blockIdx.x];
+    double s = 0.0;
+    for (int i = b0 + threadIdx.x; i < b1; i += 256) s += part[i];
+    s = block_sum_f64(s, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
 dim3 grid_for(long long n) {
     long long b = cdiv(n, 256);
     if (b > 65536) b = 65536;
@@ -146,6 +157,11 @@ hipError_t launch_interior_copy(const void *src, void *dst, int eb, const Geom &
     else
         hipLaunchKernelGGL(interior_copy_kernel<float>, grid_for(n), dim3(256), 0, s, (const float *)src,
                            (float *)dst, h, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_segment_sums(const double *part, const int *seg, int count, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(segment_sums_kernel, dim3(count), dim3(256), 0, s, part, seg, count, out);
     return hipGetLastError();
 }
 

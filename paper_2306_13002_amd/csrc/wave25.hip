@@ -232,6 +232,6 @@ hipError_t w25_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 
 }  // namespace
 
-KindOps wave25_ops = {w25_tile_ok, w25_sat_tiles, w25_nblocks, w25_launch};
+KindOps wave25_ops = {w25_tile_ok, w25_sat_tiles, w25_nblocks, w25_launch, nullptr};
 
 }  // namespace stn

@@ -68,8 +68,11 @@ def lib():
         L.stencil_profile_enable.argtypes = [vp, i32]
         L.stencil_profile_read.argtypes = [vp, dp, ctypes.POINTER(i32)]
         L.stencil_destroy.argtypes = [vp]
+        L.stencil_plan_batch.argtypes = [ctypes.POINTER(StencilDesc), i32, ctypes.POINTER(vp)]
+        L.stencil_residuals.argtypes = [vp, dp, i32, vp]
         for f in (L.stencil_plan, L.stencil_run, L.stencil_residual, L.stencil_plan_config,
-                  L.stencil_profile_enable, L.stencil_profile_read, L.stencil_destroy):
+                  L.stencil_profile_enable, L.stencil_profile_read, L.stencil_destroy, L.stencil_plan_batch,
+                  L.stencil_residuals):
             f.restype = ctypes.c_int
         L.stencil_last_error.restype = ctypes.c_char_p
         L.stencil_last_error.argtypes = []
@@ -223,6 +226,81 @@ class Plan:
                                          ctypes.byref(m)))
         return {"variant": VARIANT_NAMES[v.value], "tile": (tx.value, ty.value, zb.value),
                 "tile_map": TILE_MAP_NAMES.get(m.value, m.value)}
+
+    def profile(self, enable: bool = True):
+        _check(lib().stencil_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int32()
+        _check(lib().stencil_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().stencil_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class BatchPlan:
+    """Many independent HEAT3D7 grids run as one graph (stencil_plan_batch).
+    problems: list of interior extents (nx, ny, nz); every problem uses the
+    same coefficients and the form/tuning options given here."""
+
+    def __init__(self, problems, coef=(0.4, 0.1), **kw):
+        self.n = [tuple(int(v) for v in p) for p in problems]
+        descs = (StencilDesc * len(self.n))()
+        keep = []
+        for i, n in enumerate(self.n):
+            d, k = make_desc("heat3d7", n, coef=coef, **kw)
+            descs[i] = d
+            keep.append(k)
+        h = ctypes.c_void_p()
+        _check(lib().stencil_plan_batch(descs, len(self.n), ctypes.byref(h)))
+        del keep
+        self._h = h
+        self._plans = [Plan.__new__(Plan) for _ in self.n]
+        for p, n in zip(self._plans, self.n):  # layout checkers only (no library handle)
+            p.kind, p.n, p.dtype, p.radius, p.pitch, p._h = "heat3d7", n, "f64", 1, (0, 0), None
+
+    def run(self, fields, iterations: int = 1, stream=None):
+        """fields: one (state, scratch) pair of padded tensors per problem."""
+        if len(fields) != len(self.n):
+            raise ValueError(f"{len(self.n)} field pairs are required")
+        flat = []
+        for i, (pair, chk) in enumerate(zip(fields, self._plans)):
+            flat += [chk._check_tensor(pair[0], "f64", f"problem {i} fields[0]"),
+                     chk._check_tensor(pair[1], "f64", f"problem {i} fields[1]")]
+        fp = (ctypes.c_void_p * len(flat))(*flat)
+        _check(lib().stencil_run(self._h, fp, None, int(iterations), ctypes.c_void_p(_stream_handle(stream))))
+
+    def config(self) -> dict:
+        """Form and launch shape of the first size class."""
+        v, tx, ty, zb, m = (ctypes.c_int32() for _ in range(5))
+        _check(lib().stencil_plan_config(self._h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(zb),
+                                         ctypes.byref(m)))
+        return {"variant": VARIANT_NAMES[v.value], "tile": (tx.value, ty.value, zb.value), "tile_map": "batch"}
+
+    def residuals(self, stream=None):
+        out = (ctypes.c_double * len(self.n))()
+        _check(lib().stencil_residuals(self._h, out, len(self.n), ctypes.c_void_p(_stream_handle(stream))))
+        return list(out)
+
+    def residual(self, stream=None) -> float:
+        out = ctypes.c_double()
+        _check(lib().stencil_residual(self._h, ctypes.byref(out), ctypes.c_void_p(_stream_handle(stream))))
+        return out.value
 
     def profile(self, enable: bool = True):
         _check(lib().stencil_profile_enable(self._h, 1 if enable else 0))
