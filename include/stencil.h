@@ -183,6 +183,39 @@ stencil_status stencil_plan_config(stencil_plan_t p, int32_t *variant, int32_t *
 stencil_status stencil_profile_enable(stencil_plan_t p, int32_t enable);
 stencil_status stencil_profile_read(stencil_plan_t p, double *sweep_ms, int32_t *sweeps);
 
+/* ---- cost model (learned launch-shape picker, used by STENCIL_TUNE_MODEL) ----
+ * The model is an FP32 MLP 24 -> 64 -> 64 -> 1 (ReLU) predicting the log of
+ * seconds per sweep from 24 static features of a (stencil, form, shape).  A
+ * model is 24 feature means, 24 standard deviations and 5825 parameters (W1
+ * 64x24 row-major by unit, b1, W2 64x64, b2, w3, b3).  MODEL tuning loads a
+ * JSON model file ("mean", "std", "params" arrays) from STENCIL_COST_MODEL or
+ * cost_model.json beside libstencil.so, scores every candidate on the device
+ * and keeps the lowest prediction; without a usable file it falls back to
+ * exhaustive tuning. */
+
+/* The candidates the tuners consider for d (fields of d left 0 / AUTO are
+ * open).  Writes up to max rows of 5 ints (variant, tile_x, tile_y, zblock,
+ * tile_map) to out (host) and the total count to *n.  Host only. */
+stencil_status stencil_candidates(const stencil_desc *d, int32_t max, int32_t *out, int32_t *n);
+
+/* The 24 features of d run with one candidate, into out[24] (host).  Host only. */
+stencil_status stencil_features(const stencil_desc *d, int32_t variant, int32_t tile_x, int32_t tile_y,
+                                int32_t zblock, int32_t tile_map, float *out);
+
+/* Train on the device: X (n x 24 raw features, row-major, host), y (n log
+ * seconds, host), init (5825 initial parameters, host).  Features are
+ * standardized with the rows' mean and standard deviation (0 -> 1), then
+ * `epochs` full-batch Adam steps (lr; beta1 0.9, beta2 0.999, eps 1e-8) on the
+ * mean squared error run as a replayed hipGraph of one epoch.  Writes the
+ * model (24 + 24 + 5825 floats) to model_out and, if loss_out is not NULL,
+ * the loss before each step.  Synchronizes `stream`. */
+stencil_status stencil_mlp_train(const float *X, const float *y, int32_t n, const float *init, int32_t epochs,
+                                 float lr, float *model_out, float *loss_out, void *stream);
+
+/* Predictions (log seconds) of a model for n rows of raw features (host in,
+ * host out).  Synchronizes `stream`. */
+stencil_status stencil_mlp_predict(const float *model, const float *X, int32_t n, float *y_out, void *stream);
+
 /* Release a plan and its buffers (waits for nothing; the caller must not
  * destroy a plan while its work is in flight).  NULL is accepted. */
 stencil_status stencil_destroy(stencil_plan_t p);

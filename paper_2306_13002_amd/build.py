@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libstencil.so")
-SOURCES = ["abi.cpp", "tune.cpp", "batch.cpp", "support.hip", "heat.hip", "poisson19.hip", "wave25.hip", "generic.hip"]
+SOURCES = ["abi.cpp", "tune.cpp", "batch.cpp", "support.hip", "heat.hip", "poisson19.hip", "wave25.hip", "generic.hip", "costmodel.hip", "costmodel_host.cpp"]
 ARCH = os.environ.get("STENCIL_OFFLOAD_ARCH", "gfx950")
 
 CXXFLAGS = [
@@ -53,7 +53,7 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         list(ex.map(lambda so: _compile(*so), zip(SOURCES, objs)))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-ldl"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

@@ -1,0 +1,175 @@
+"""Timing campaign, training and scoring of the learned cost model.
+
+    python -m paper_2306_13002_amd.costmodel collect --out DIR [--first I --last J]
+    python -m paper_2306_13002_amd.costmodel train --data DIR --model FILE
+    python -m paper_2306_13002_amd.costmodel score --data DIR --model FILE
+
+collect: for the three fixed workloads (heat2d5 256^2, poisson19 129x129x257,
+wave25 512^3) and the seeded generic corpus (stencils 0..249, grid edges
+capped at 160 for timing), time every candidate the tuners consider --
+median of 3 single-sweep runs after a warm-up, HIP events through the
+library's profiling hook -- and store its 24 features (computed by the
+library) with log(seconds per sweep).  Stencils 0..199 and the fixed
+workloads train; 200..249 are held out.
+
+train: full-batch Adam on the device through stencil_mlp_train (2000
+epochs, lr 1e-3, seeded initial weights); writes the model JSON that
+STENCIL_TUNE_MODEL plans load.
+
+score: for each held-out stencil, the candidate with the lowest predicted
+time against the fastest measured one (same session's timings): geometric
+mean, worst case and fraction within 10 %.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import synth
+from . import stencil as S
+
+TIMING_EDGE_CAP = 160
+FIXED = ("heat2d5", "poisson19", "wave25")
+
+
+def stencil_spec(name):
+    """(kind, n, plan kwargs, builder of device fields) for a workload name
+    ('heat2d5', 'poisson19', 'wave25' or 'g<index>')."""
+    if name == "heat2d5":
+        return "heat2d5", (256, 256), dict(coef=(0.6, 0.1))
+    if name == "poisson19":
+        return "poisson19", (127, 127, 255), dict(omega=0.8)
+    if name == "wave25":
+        return "wave25", (512, 512, 512), dict(coef=synth.WAVE25_COEF)
+    s = synth.generic_stencil(int(name[1:]), max_edge=TIMING_EDGE_CAP)
+    return "generic", s["n"], dict(dtype=s["dtype"], radius=s["radius"], coef=s["coef"], taps=s["taps"],
+                                   cids=s["cids"])
+
+
+def device_inputs(name, kind, n, kw, torch, dev):
+    if kind == "heat2d5":
+        u = synth.heat2d5_input(256)
+        return [torch.tensor(u, device=dev), torch.empty(u.shape, dtype=torch.float64, device=dev)], None
+    if kind == "poisson19":
+        p, cf = synth.poisson19_inputs()
+        return ([torch.tensor(p, device=dev), torch.empty(p.shape, dtype=torch.float32, device=dev)],
+                [torch.tensor(c, device=dev) for c in cf])
+    if kind == "wave25":
+        a, b, v = synth.wave25_inputs(512)
+        return [torch.tensor(a, device=dev), torch.tensor(b, device=dev)], [torch.tensor(v, device=dev)]
+    u = synth.generic_input(n, kw["radius"], kw["dtype"], stream=3000 + int(name[1:]))
+    dt = torch.float32 if kw["dtype"] == "f32" else torch.float64
+    return [torch.tensor(u, device=dev), torch.empty(u.shape, dtype=dt, device=dev)], None
+
+
+def time_candidate(kind, n, kw, cand, fields, coefs, torch, reps=3):
+    v, tile, m = cand
+    p = S.Plan(kind, n, variant=v, tile=tile, tile_map=m, **kw)
+    p.profile(True)
+    p.run(fields, coefs, iterations=1)
+    ts = []
+    for _ in range(reps):
+        p.run(fields, coefs, iterations=1)
+        ms, k = p.profile_read()
+        ts.append(ms / k)
+    p.close()
+    return float(np.median(ts)) * 1e-3  # seconds per sweep
+
+
+def collect(out, names):
+    import torch
+    dev = torch.device("cuda:0")
+    os.makedirs(out, exist_ok=True)
+    for name in names:
+        path = os.path.join(out, f"{name}.npz")
+        if os.path.exists(path):
+            continue
+        t0 = time.time()
+        kind, n, kw = stencil_spec(name)
+        fields, coefs = device_inputs(name, kind, n, kw, torch, dev)
+        cands = S.candidates(kind, n, **kw)
+        X = np.stack([S.features(kind, n, c, **kw) for c in cands])
+        secs = np.array([time_candidate(kind, n, kw, c, fields, coefs, torch) for c in cands])
+        np.savez(path, X=X, y=np.log(secs), secs=secs,
+                 cands=np.array([json.dumps(c) for c in cands]), n=np.array(n))
+        del fields, coefs
+        torch.cuda.empty_cache()
+        best = int(np.argmin(secs))
+        print(f"{name}: {kind} n={tuple(n)} {len(cands)} candidates, best {cands[best]} {secs[best] * 1e6:.1f} us, "
+              f"{time.time() - t0:.1f} s", flush=True)
+
+
+def load(data, names):
+    rows = []
+    for name in names:
+        z = np.load(os.path.join(data, f"{name}.npz"))
+        rows.append((name, z["X"], z["y"], z["secs"], [json.loads(c) for c in z["cands"]]))
+    return rows
+
+
+def train(data, model_path, epochs=2000, lr=1e-3, train_names=None):
+    names = train_names or (list(FIXED) + [f"g{i}" for i in range(200)])
+    names = [nm for nm in names if os.path.exists(os.path.join(data, f"{nm}.npz"))]
+    rows = load(data, names)
+    X = np.concatenate([r[1] for r in rows]).astype(np.float32)
+    y = np.concatenate([r[2] for r in rows]).astype(np.float32)
+    model, loss = S.mlp_train(X, y, synth.mlp_init(), epochs, lr)
+    doc = {"n_features": 24, "hidden": 64, "epochs": epochs, "lr": lr, "train_rows": int(X.shape[0]),
+           "train_stencils": len(rows), "final_loss": float(loss[-1]) if len(loss) else None,
+           "mean": [float(v) for v in model[:24]], "std": [float(v) for v in model[24:48]],
+           "params": [float(v) for v in model[48:]]}
+    with open(model_path, "w") as f:
+        json.dump(doc, f)
+    print(f"trained on {X.shape[0]} rows from {len(rows)} stencils; loss {loss[0]:.4f} -> {loss[-1]:.4f}", flush=True)
+    return model, loss
+
+
+def read_model(path):
+    d = json.load(open(path))
+    return np.array(d["mean"] + d["std"] + d["params"], dtype=np.float32)
+
+
+def score(data, model_path, names=None):
+    names = names or [f"g{i}" for i in range(200, 250)]
+    names = [nm for nm in names if os.path.exists(os.path.join(data, f"{nm}.npz"))]
+    model = read_model(model_path)
+    ratios = []
+    for name, X, y, secs, cands in load(data, names):
+        pred = S.mlp_predict(model, X)
+        pick = int(np.argmin(pred))
+        ratios.append(secs[pick] / secs.min())
+    r = np.array(ratios)
+    res = {"held_out": len(r), "geomean_pick_over_best": float(np.exp(np.mean(np.log(r)))),
+           "worst": float(r.max()), "frac_within_10pct": float(np.mean(r <= 1.10))}
+    print(json.dumps(res), flush=True)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["collect", "train", "score"])
+    ap.add_argument("--out", default="gpurun_out/campaign")
+    ap.add_argument("--data", default="gpurun_out/campaign")
+    ap.add_argument("--model", default=os.path.join(os.path.dirname(__file__), "cost_model.json"))
+    ap.add_argument("--first", type=int, default=0)
+    ap.add_argument("--last", type=int, default=249)
+    ap.add_argument("--fixed", action="store_true", help="also time the three fixed workloads")
+    ap.add_argument("--epochs", type=int, default=2000)
+    a = ap.parse_args()
+    if a.cmd == "collect":
+        names = (list(FIXED) if a.fixed else []) + [f"g{i}" for i in range(a.first, a.last + 1)]
+        collect(a.out, names)
+    elif a.cmd == "train":
+        train(a.data, a.model, epochs=a.epochs)
+    else:
+        score(a.data, a.model)
+
+
+if __name__ == "__main__":
+    main()

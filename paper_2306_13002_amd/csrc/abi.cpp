@@ -290,7 +290,21 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     if (d->variant == STENCIL_SATURATED && !has_sat)
         return fail(STENCIL_E_UNSUPPORTED, "kind %d has no saturated form", p->kind);
     const bool open = d->variant == STENCIL_AUTO || !d->tile_x || !d->tile_y || !d->zblock || !d->tile_map;
-    if (d->tune == STENCIL_TUNE_EXHAUSTIVE && open) {
+    if (d->tune == STENCIL_TUNE_MODEL && open) {
+        TuneRequest rq{has_sat ? d->variant : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map};
+        TuneEntry e{};
+        stencil_status st = tune_model(p, rq, &e);
+        if (st == STENCIL_OK) {
+            p->variant = e.variant;
+            p->tile = e.tile;
+            p->remap = e.remap;
+            p->tuned = true;
+            return STENCIL_OK;
+        }
+        if (st != STENCIL_E_STATE) return st;
+        logf("%s; falling back to exhaustive tuning", stencil_last_error());
+    }
+    if ((d->tune == STENCIL_TUNE_EXHAUSTIVE || d->tune == STENCIL_TUNE_MODEL) && open) {
         TuneRequest rq{has_sat ? d->variant : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map};
         const std::string key = tune_key(p, rq);
         TuneEntry e{};
@@ -331,8 +345,6 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out) {
     int rz = 0;
     stencil_status st = validate_desc(d, g, rz);
     if (st != STENCIL_OK) return st;
-    if (d->tune == STENCIL_TUNE_MODEL)
-        return fail(STENCIL_E_UNSUPPORTED, "tune mode MODEL is not available in this build");
     // device
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -347,6 +359,7 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out) {
     p->omega = d->omega;
     p->ops = ops_for(d->kind);
     for (int c = 0; c < 5; ++c) p->c[c] = (d->coef && c < d->n_coef) ? d->coef[c] : 0.0;
+    p->info = stencil_info(d, g);
     p->base_args.g = g;
     for (int c = 0; c < 5; ++c) p->base_args.c[c] = p->c[c];
     p->base_args.omega = d->omega;

@@ -5,6 +5,7 @@
 
 #include "../../include/stencil.h"
 #include "internal.hpp"
+#include "tune.hpp"
 
 #include <vector>
 
@@ -58,4 +59,5 @@ struct stencil_plan_s {
     void *d_tab = nullptr;       // GENERIC: device tap tables
     bool tuned = false;          // configuration came from the autotuner
     BatchState *batch = nullptr; // non-null for plans made by stencil_plan_batch
+    stn::StencilInfo info{};     // static description (cost-model features)
 };

@@ -74,15 +74,10 @@ const Tile kPlainTiles[] = {{64, 4, 1},  {64, 2, 2},  {128, 2, 1}, {256, 1, 1}, 
                             {64, 8, 1},  {128, 4, 1}, {128, 8, 1}, {256, 2, 1}};
 const int kZblocks[] = {4, 8, 16, 32, 64, 128, 256};
 
-struct Cand {
-    int variant;
-    Tile tile;
-    int remap;
-};
+}  // namespace
 
-std::vector<Cand> candidates(const stencil_plan_s *p, const TuneRequest &rq) {
+std::vector<Cand> tune_candidates(const KindOps *ops, int kind, const Geom &g, const TuneRequest &rq) {
     std::vector<Cand> out;
-    const KindOps *ops = p->ops;
     auto want_v = [&](int v) { return rq.variant == STENCIL_AUTO || rq.variant == v; };
     auto tile_fits = [&](const Tile &t) {
         return (!rq.tile_x || rq.tile_x == t.tx) && (!rq.tile_y || rq.tile_y == t.ty) &&
@@ -90,14 +85,21 @@ std::vector<Cand> candidates(const stencil_plan_s *p, const TuneRequest &rq) {
     };
     if (want_v(V_PLAIN))
         for (const Tile &t : kPlainTiles)
-            if (ops->tile_ok(V_PLAIN, t) && tile_fits(t)) out.push_back({V_PLAIN, t, 1});
+            if (ops->tile_ok(V_PLAIN, t) && tile_fits(t)) out.push_back({V_PLAIN, t, 0});
     if (want_v(V_SATURATED) && ops->sat_tiles) {
         Tile st[64];
         const int ns = ops->sat_tiles(st, 64);
         std::vector<int> zbs;
-        for (int zb : kZblocks)
-            if (zb < p->g.nz) zbs.push_back(zb);
-        zbs.push_back(p->g.nz);
+        if (kind == STENCIL_GENERIC) {
+            // pruned: generic kernels re-read no plane, so z depth only trades
+            // priming against block count
+            for (int zb : {16, 64})
+                if (zb < g.nz) zbs.push_back(zb);
+        } else {
+            for (int zb : kZblocks)
+                if (zb < g.nz) zbs.push_back(zb);
+        }
+        zbs.push_back(g.nz);
         for (int s = 0; s < ns; ++s)
             for (int zb : zbs) {
                 Tile t{st[s].tx, st[s].ty, zb};
@@ -108,6 +110,8 @@ std::vector<Cand> candidates(const stencil_plan_s *p, const TuneRequest &rq) {
     }
     return out;
 }
+
+namespace {
 
 struct Buffers {
     void *f[2] = {nullptr, nullptr};
@@ -176,7 +180,7 @@ static double time_one(const stencil_plan_s *p, const Cand &c, Buffers &b, hipSt
 }
 
 stencil_status tune_exhaustive(stencil_plan_s *p, const TuneRequest &rq, TuneEntry *best) {
-    const std::vector<Cand> cands = candidates(p, rq);
+    const std::vector<Cand> cands = tune_candidates(p->ops, p->kind, p->g, rq);
     if (cands.empty()) return fail(STENCIL_E_UNSUPPORTED, "no launch shape matches the requested tile fields");
     const int eb = elem_bytes(p->dtype);
     const long long span = (long long)(p->g.PZ() - 1) * p->g.pz * (p->rz ? 1 : 0) +

@@ -2,6 +2,9 @@
 #pragma once
 
 #include <string>
+#include <vector>
+
+#include "../../include/stencil.h"
 
 #include "internal.hpp"
 
@@ -21,6 +24,30 @@ struct TuneEntry {
     int remap;    // 0 natural, 1 XCD-chunked
     double us;    // median time per sweep of the winner
 };
+
+// One launch candidate: form, shape and tile map (remap 1 = XCD-chunked).
+struct Cand {
+    int variant;
+    Tile tile;
+    int remap;
+};
+
+// Static description of a stencil used by the cost model's features.
+struct StencilInfo {
+    int kind, dtype, eb, r;
+    Geom g;
+    int n_taps;        // points read per update from the state grid
+    int n_coef;        // distinct coefficients (coefficient arrays for POISSON19)
+    int n_groups;      // saturated tap groups (GENERIC), else distinct coefficients
+    double box_frac;   // fraction of taps with two or more nonzero offsets
+};
+
+StencilInfo stencil_info(const stencil_desc *d, const Geom &g);
+// Candidates the tuners consider for a plan's kind and geometry, restricted
+// by the request's fixed fields.
+std::vector<Cand> tune_candidates(const KindOps *ops, int kind, const Geom &g, const TuneRequest &rq);
+void cost_features(const StencilInfo &si, const Cand &c, float out[24]);
+stencil_status tune_model(stencil_plan_s *p, const TuneRequest &rq, TuneEntry *best);
 
 std::string tune_key(const stencil_plan_s *p, const TuneRequest &rq);
 bool tune_lookup(const std::string &key, TuneEntry *out);

@@ -70,9 +70,15 @@ def lib():
         L.stencil_destroy.argtypes = [vp]
         L.stencil_plan_batch.argtypes = [ctypes.POINTER(StencilDesc), i32, ctypes.POINTER(vp)]
         L.stencil_residuals.argtypes = [vp, dp, i32, vp]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.stencil_candidates.argtypes = [ctypes.POINTER(StencilDesc), i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.stencil_features.argtypes = [ctypes.POINTER(StencilDesc), i32, i32, i32, i32, i32, fp]
+        L.stencil_mlp_train.argtypes = [fp, fp, i32, fp, i32, ctypes.c_float, fp, fp, vp]
+        L.stencil_mlp_predict.argtypes = [fp, fp, i32, fp, vp]
         for f in (L.stencil_plan, L.stencil_run, L.stencil_residual, L.stencil_plan_config,
                   L.stencil_profile_enable, L.stencil_profile_read, L.stencil_destroy, L.stencil_plan_batch,
-                  L.stencil_residuals):
+                  L.stencil_residuals, L.stencil_candidates, L.stencil_features, L.stencil_mlp_train,
+                  L.stencil_mlp_predict):
             f.restype = ctypes.c_int
         L.stencil_last_error.restype = ctypes.c_char_p
         L.stencil_last_error.argtypes = []
@@ -326,3 +332,63 @@ class BatchPlan:
 
     def __exit__(self, *a):
         self.close()
+
+
+# ---------------------------------------------------------------- cost model
+N_FEATURES = 24
+N_MLP_PARAMS = 5825
+
+
+def candidates(kind: str, n, **kw):
+    """The launch candidates the tuners consider: list of
+    (variant, (tile_x, tile_y, zblock), tile_map) with names."""
+    d, keep = make_desc(kind, n, **kw)
+    cnt = ctypes.c_int32()
+    _check(lib().stencil_candidates(ctypes.byref(d), 0, None, ctypes.byref(cnt)))
+    buf = (ctypes.c_int32 * (5 * max(1, cnt.value)))()
+    _check(lib().stencil_candidates(ctypes.byref(d), cnt.value, buf, ctypes.byref(cnt)))
+    out = []
+    for i in range(cnt.value):
+        v, tx, ty, zb, m = buf[5 * i:5 * i + 5]
+        out.append((VARIANT_NAMES[v], (tx, ty, zb), TILE_MAP_NAMES[m]))
+    return out
+
+
+def features(kind: str, n, cand, **kw):
+    """The 24 cost-model features of a stencil run with one candidate."""
+    import numpy as np
+    d, keep = make_desc(kind, n, **kw)
+    v, (tx, ty, zb), m = cand
+    out = (ctypes.c_float * N_FEATURES)()
+    _check(lib().stencil_features(ctypes.byref(d), VARIANTS[v], tx, ty, zb, TILE_MAPS[m], out))
+    return np.array(out[:], dtype=np.float32)
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def mlp_train(X, y, init, epochs: int, lr: float = 1e-3, stream=None):
+    """Train the cost-model MLP on the device (see stencil_mlp_train).
+    Returns (model vector of 24 + 24 + 5825 floats, loss before each step)."""
+    import numpy as np
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    th = np.ascontiguousarray(init, dtype=np.float32)
+    if X.ndim != 2 or X.shape[1] != N_FEATURES or y.shape != (X.shape[0],) or th.shape != (N_MLP_PARAMS,):
+        raise ValueError("X must be n x 24, y n, init 5825")
+    model = np.zeros(2 * N_FEATURES + N_MLP_PARAMS, dtype=np.float32)
+    loss = np.zeros(max(1, epochs), dtype=np.float32)
+    _check(lib().stencil_mlp_train(_fptr(X), _fptr(y), X.shape[0], _fptr(th), int(epochs), float(lr), _fptr(model),
+                                   _fptr(loss), ctypes.c_void_p(_stream_handle(stream))))
+    return model, loss[:epochs]
+
+
+def mlp_predict(model, X, stream=None):
+    import numpy as np
+    model = np.ascontiguousarray(model, dtype=np.float32)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    out = np.zeros(X.shape[0], dtype=np.float32)
+    _check(lib().stencil_mlp_predict(_fptr(model), _fptr(X), X.shape[0], _fptr(out),
+                                     ctypes.c_void_p(_stream_handle(stream))))
+    return out

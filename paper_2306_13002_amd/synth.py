@@ -254,3 +254,15 @@ def generic_input(n, r: int, dtype: str, seed: int = 5, stream: int = 1000):
     if dtype == "f32":
         return uniform_f32(seed, stream, shape)
     return uniform_f64(seed, stream, shape)
+
+
+def mlp_init(seed: int = 5, stream: int = 7000):
+    """Initial cost-model parameters (5825): weights U(-sqrt(6/fan_in),
+    sqrt(6/fan_in)) in the layout W1 (64x24), b1, W2 (64x64), b2, w3, b3;
+    biases 0."""
+    u = uniform_f64(seed, stream, (24 * 64 + 64 * 64 + 64,))
+    w1 = (2 * u[:1536] - 1) * np.sqrt(6 / 24)
+    w2 = (2 * u[1536:1536 + 4096] - 1) * np.sqrt(6 / 64)
+    w3 = (2 * u[1536 + 4096:] - 1) * np.sqrt(6 / 64)
+    z = np.zeros(64)
+    return np.concatenate([w1, z, w2, z, w3, [0.0]]).astype(np.float32)

