@@ -59,6 +59,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                                "python -m paper_2306_13002_amd.build")
+        # torch ships its own HIP runtime under the same soname as the one
+        # libstencil.so links; importing torch first makes the process load a
+        # single runtime that both use (loading libstencil.so first leaves
+        # torch's later initialization with a second, unusable one).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
         L.stencil_plan.argtypes = [ctypes.POINTER(StencilDesc), ctypes.POINTER(vp)]
