@@ -139,14 +139,28 @@ def score(data, model_path, names=None):
     names = names or [f"g{i}" for i in range(200, 250)]
     names = [nm for nm in names if os.path.exists(os.path.join(data, f"{nm}.npz"))]
     model = read_model(model_path)
-    ratios = []
+    ratios, paper, default = [], [], []
     for name, X, y, secs, cands in load(data, names):
         pred = S.mlp_predict(model, X)
         pick = int(np.argmin(pred))
         ratios.append(secs[pick] / secs.min())
+        # reference pickers: the paper's static cost (feature 21) alone, first
+        # minimum in candidate order; and the library's untuned default shape
+        paper.append(secs[int(np.argmin(X[:, 21]))] / secs.min())
+        dflt = [i for i, c in enumerate(cands) if c[0] == "saturated" and tuple(c[1][:2]) == (64, 4)
+                and c[1][2] == 16 and c[2] == "xcd"]
+        if dflt:
+            default.append(secs[dflt[0]] / secs.min())
+
+    def summary(r):
+        r = np.array(r)
+        return {"geomean": float(np.exp(np.mean(np.log(r)))), "worst": float(r.max()),
+                "frac_within_10pct": float(np.mean(r <= 1.10))}
+
     r = np.array(ratios)
     res = {"held_out": len(r), "geomean_pick_over_best": float(np.exp(np.mean(np.log(r)))),
-           "worst": float(r.max()), "frac_within_10pct": float(np.mean(r <= 1.10))}
+           "worst": float(r.max()), "frac_within_10pct": float(np.mean(r <= 1.10)),
+           "paper_static_cost_picker": summary(paper), "untuned_default": summary(default) if default else None}
     print(json.dumps(res), flush=True)
     return res
 
