@@ -90,7 +90,25 @@ typedef enum {
 } stencil_kind;
 
 typedef enum { STENCIL_F32 = 1, STENCIL_F64 = 2 } stencil_dtype; /* storage type */
-typedef enum { STENCIL_PLAIN = 0, STENCIL_SATURATED = 1, STENCIL_AUTO = 2 } stencil_variant;
+/* PLAIN and SATURATED are the two forms (see the top of this file); AUTO lets
+ * the plan choose between them.  The per-point ablation forms of the paper's
+ * evaluation (Sec. Evaluation: CSE, CSE+SAT, CSE+BULK, ACCSAT) exist for WAVE25
+ * and POISSON19, one thread per point with every operand from memory (CSE is
+ * PLAIN: no address is loaded twice in these bodies):
+ *   CSE_SAT       the saturated arithmetic, loads where first used;
+ *   CSE_BULK      all loads first in ascending address order, plain arithmetic
+ *                 (bit-identical to PLAIN);
+ *   ACCSAT_POINT  both (bit-identical to CSE_SAT and to SATURATED, which adds
+ *                 the z-streaming register queue and LDS tile).
+ * They use the plain launch shapes and are never picked by the tuners. */
+typedef enum {
+    STENCIL_PLAIN = 0,
+    STENCIL_SATURATED = 1,
+    STENCIL_AUTO = 2,
+    STENCIL_CSE_SAT = 3,
+    STENCIL_CSE_BULK = 4,
+    STENCIL_ACCSAT_POINT = 5
+} stencil_variant;
 /* How a plan picks variant and tile when variant == AUTO or a tile field is 0:
  * FIXED uses library defaults; EXHAUSTIVE times every candidate on the device
  * (results cached per size class); MODEL asks the learned cost model. */

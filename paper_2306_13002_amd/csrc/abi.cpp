@@ -150,6 +150,9 @@ stencil_status build_generic_tables(stencil_plan_s *p, const stencil_desc *d) {
     t.g_t = di + o_gt;
     t.g_c = dd + c.size();
     t.t_xy = di + o_xy;
+    t.corners = false;
+    for (int k = 0; k < n; ++k)
+        if (d->tap_off[3 * k] != 0 && d->tap_off[3 * k + 1] != 0) t.corners = true;
     return STENCIL_OK;
 }
 
@@ -162,8 +165,10 @@ stencil_status validate_desc(const stencil_desc *d, Geom &g, int &rz) {
     const int k = d->kind;
     if (k < STENCIL_HEAT2D5 || k > STENCIL_GENERIC) return fail(STENCIL_E_INVAL, "unknown kind %d", k);
     if (d->dtype != STENCIL_F32 && d->dtype != STENCIL_F64) return fail(STENCIL_E_INVAL, "unknown dtype %d", d->dtype);
-    if (d->variant < STENCIL_PLAIN || d->variant > STENCIL_AUTO)
+    if (d->variant < STENCIL_PLAIN || d->variant > STENCIL_ACCSAT_POINT)
         return fail(STENCIL_E_INVAL, "unknown variant %d", d->variant);
+    if (d->variant >= STENCIL_CSE_SAT && k != STENCIL_WAVE25 && k != STENCIL_POISSON19)
+        return fail(STENCIL_E_UNSUPPORTED, "the per-point ablation forms are offered for WAVE25 and POISSON19");
     if (d->tune < STENCIL_TUNE_FIXED || d->tune > STENCIL_TUNE_MODEL)
         return fail(STENCIL_E_INVAL, "unknown tune mode %d", d->tune);
     if (d->bc != STENCIL_BC_DIRICHLET && d->bc != STENCIL_BC_PERIODIC)
@@ -289,7 +294,8 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     if (d->tile_map < 0 || d->tile_map > 2) return fail(STENCIL_E_INVAL, "tile_map %d not in 0..2", d->tile_map);
     if (d->variant == STENCIL_SATURATED && !has_sat)
         return fail(STENCIL_E_UNSUPPORTED, "kind %d has no saturated form", p->kind);
-    const bool open = d->variant == STENCIL_AUTO || !d->tile_x || !d->tile_y || !d->zblock || !d->tile_map;
+    const bool open = d->variant < STENCIL_CSE_SAT &&
+                      (d->variant == STENCIL_AUTO || !d->tile_x || !d->tile_y || !d->zblock || !d->tile_map);
     if (d->tune == STENCIL_TUNE_MODEL && open) {
         TuneRequest rq{has_sat ? d->variant : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map};
         TuneEntry e{};
@@ -321,7 +327,7 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     }
     int v = d->variant;
     if (v == STENCIL_AUTO) v = has_sat ? V_SATURATED : V_PLAIN;
-    Tile t = default_tile(p->kind, v, p->g);
+    Tile t = default_tile(p->kind, v >= V_CSE_SAT ? V_PLAIN : v, p->g);
     if (d->tile_x) t.tx = d->tile_x;
     if (d->tile_y) t.ty = d->tile_y;
     if (d->zblock) t.tz = d->zblock;

@@ -49,7 +49,7 @@ __global__ void generic_plain(const T *__restrict__ src, T *__restrict__ dst, Ge
     }
 }
 
-template <typename T, int R, int TX, int TY>
+template <typename T, int R, int TX, int TY, bool CORNERS>
 __global__ __launch_bounds__(TX *TY) void generic_sat(const T *__restrict__ src, T *__restrict__ dst, Geom g,
                                                       GenTab tab, int zb, int remap, double *__restrict__ part) {
     constexpr int W = TX + 2 * R, NT = TX * TY, PLANE = (TY + 2 * R) * W, NQ = 2 * R + 1;
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(TX *TY) void generic_sat(const T *__restrict__ src,
     const long long col = (long long)yp * g.py + xp;
     const int me = (ty + R) * W + (tx + R);
 
-    HaloStager<T, TX, TY, R, true, NT> halo;
+    HaloStager<T, TX, TY, R, CORNERS, NT> halo;
     halo.init(tid, bx * TX + R, by * TY + R, g.py, PX, PY);
 
     // acc[s]: output plane m + R - s after input plane m; ctr[s]: that
@@ -115,13 +115,27 @@ __global__ __launch_bounds__(TX *TY) void generic_sat(const T *__restrict__ src,
             double a = acc[s];
             for (int gi = g0; gi < g1; ++gi) {
                 const int t0 = tab.g_t[gi], t1 = tab.g_t[gi + 1];
-                double sum = 0.0;
-                for (int ti = t0; ti < t1; ++ti) {
-                    const int xy = tab.t_xy[ti];
-                    const int dx = (short)(xy & 0xFFFF), dy = xy >> 16;
-                    sum += t[me + dy * W + dx];
+                // the group's taps (ascending address): eight LDS reads in
+                // flight, four independent partial sums, then one FMA
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                int ti = t0;
+                for (; ti + 8 <= t1; ti += 8) {
+                    double v[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int xy = tab.t_xy[ti + q];
+                        v[q] = t[me + (xy >> 16) * W + (short)(xy & 0xFFFF)];
+                    }
+                    s0 += v[0] + v[4];
+                    s1 += v[1] + v[5];
+                    s2 += v[2] + v[6];
+                    s3 += v[3] + v[7];
                 }
-                a = fma(tab.g_c[gi], sum, a);
+                for (; ti < t1; ++ti) {
+                    const int xy = tab.t_xy[ti];
+                    s0 += t[me + (xy >> 16) * W + (short)(xy & 0xFFFF)];
+                }
+                a = fma(tab.g_c[gi], (s0 + s1) + (s2 + s3), a);
             }
             acc[s] = a;
         }
@@ -175,23 +189,24 @@ hipError_t gen_launch_t(int v, Tile t, const SweepArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(generic_plain<T>, grid, dim3(t.tx, t.ty, t.tz), 0, s, src, dst, a.g, a.gen, a.part);
         return hipGetLastError();
     }
+#define GEN_LAUNCH(A_, B_, R_, C_)                                                                          \
+    hipLaunchKernelGGL((generic_sat<T, R_, A_, B_, C_>), grid, dim3(A_, B_, 1), 0, s, src, dst, a.g, a.gen,   \
+                       t.tz, a.remap, a.part)
 #define X(A, B)                                                                                             \
     if (t.tx == A && t.ty == B) {                                                                           \
+        const bool c = a.gen.corners;                                                                       \
         switch (a.g.r) {                                                                                    \
-        case 1: hipLaunchKernelGGL((generic_sat<T, 1, A, B>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.gen, \
-                                   t.tz, a.remap, a.part); break;                                           \
-        case 2: hipLaunchKernelGGL((generic_sat<T, 2, A, B>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.gen, \
-                                   t.tz, a.remap, a.part); break;                                           \
-        case 3: hipLaunchKernelGGL((generic_sat<T, 3, A, B>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.gen, \
-                                   t.tz, a.remap, a.part); break;                                           \
-        case 4: hipLaunchKernelGGL((generic_sat<T, 4, A, B>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.gen, \
-                                   t.tz, a.remap, a.part); break;                                           \
+        case 1: if (c) GEN_LAUNCH(A, B, 1, true); else GEN_LAUNCH(A, B, 1, false); break;                               \
+        case 2: if (c) GEN_LAUNCH(A, B, 2, true); else GEN_LAUNCH(A, B, 2, false); break;                               \
+        case 3: if (c) GEN_LAUNCH(A, B, 3, true); else GEN_LAUNCH(A, B, 3, false); break;                               \
+        case 4: if (c) GEN_LAUNCH(A, B, 4, true); else GEN_LAUNCH(A, B, 4, false); break;                               \
         default: return hipErrorInvalidValue;                                                               \
         }                                                                                                   \
         return hipGetLastError();                                                                           \
     }
     GEN_SAT_TILES(X)
 #undef X
+#undef GEN_LAUNCH
     return hipErrorInvalidValue;
 }
 

@@ -7,7 +7,9 @@
 
 namespace stn {
 
-enum Variant { V_PLAIN = 0, V_SATURATED = 1 };
+// Forms.  V_CSE_SAT, V_CSE_BULK and V_ACCSAT_POINT are the per-point forms of
+// the paper's ablation (rewritten arithmetic only, bulk load only, both).
+enum Variant { V_PLAIN = 0, V_SATURATED = 1, V_CSE_SAT = 3, V_CSE_BULK = 4, V_ACCSAT_POINT = 5 };
 
 // Launch shape.  Plain forms: block = (tx, ty, tz) threads, one per point.
 // Saturated forms: tx threads along x, a tile of ty rows, zblock planes
@@ -25,6 +27,7 @@ struct GenTab {
     const int *g_t;     // saturated: taps of group g are [g_t[g], g_t[g+1])
     const double *g_c;  // saturated: coefficient of group g
     const int *t_xy;    // saturated: (dy << 16) | (dx & 0xffff) per tap, ascending address in a group
+    bool corners;       // some tap has two nonzero in-plane offsets (the staged ring needs its corners)
 };
 
 // Arguments of one sweep launch.

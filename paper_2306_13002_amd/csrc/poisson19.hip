@@ -78,6 +78,100 @@ __global__ void poisson19_plain(const float *__restrict__ p, float *__restrict__
     }
 }
 
+// Per-point forms of the paper's ablation (Sec. Evaluation), one thread per
+// point with every operand from memory; CSE is the plain form (no address
+// is loaded twice).  FORM_SAT: the saturated form's arithmetic (differences
+// of differences, one FMA chain), loads where first used.  FORM_BULK: all 31
+// loads first -- the 12 coefficients, then p in ascending address order --
+// then the plain arithmetic order.  FORM_BOTH: those loads, then FORM_SAT's
+// arithmetic.  FORM_SAT and FORM_BOTH compute exactly what the z-streaming
+// saturated kernel computes; FORM_BULK exactly what the plain kernel does.
+enum { FORM_SAT = 0, FORM_BULK = 1, FORM_BOTH = 2 };
+
+__device__ __forceinline__ double p19_sat_math(const double *cf, double pc, double pE, double pW, double pN,
+                                               double pS, double pU, double pD, double pNE, double pSE, double pNW,
+                                               double pSW, double uN, double uS, double mN, double mS, double uE,
+                                               double uW, double mE, double mW, double omega, float *out) {
+    const double B0v = (pNE - pSE) - (pNW - pSW);
+    const double B1v = (uN - uS) - (mN - mS);
+    const double B2v = (uE - uW) - (mE - mW);
+    double s0 = fma(cf[B0], B0v, cf[WRK1]);
+    s0 = fma(cf[B1], B1v, s0);
+    s0 = fma(cf[B2], B2v, s0);
+    s0 = fma(cf[A0], pE, s0);
+    s0 = fma(cf[C0], pW, s0);
+    s0 = fma(cf[A1], pN, s0);
+    s0 = fma(cf[C1], pS, s0);
+    s0 = fma(cf[A2], pU, s0);
+    s0 = fma(cf[C2], pD, s0);
+    const double ss = fma(s0, cf[A3], -pc) * cf[BND];
+    *out = (float)fma(omega, ss, pc);
+    return ss;
+}
+
+template <int FORM>
+__global__ void poisson19_point(const float *__restrict__ p, float *__restrict__ pn, P19Coef c, Geom g,
+                                double omega, double *__restrict__ part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    double d2 = 0.0;
+    if (i < g.nx && j < g.ny && k < g.nz) {
+        const long long q = (long long)(k + 1) * g.pz + (long long)(j + 1) * g.py + (i + 1);
+        const long long Y = g.py, Z = g.pz;
+        double ss;
+        float out;
+        if (FORM == FORM_SAT) {
+            double cf[12];
+#pragma unroll
+            for (int a = 0; a < 12; ++a) cf[a] = c.f[a][q];
+#define P(o) ((double)p[q + (o)])
+            ss = p19_sat_math(cf, P(0), P(1), P(-1), P(Y), P(-Y), P(Z), P(-Z), P(Y + 1), P(-Y + 1), P(Y - 1), P(-Y - 1),
+                              P(Z + Y), P(Z - Y), P(-Z + Y), P(-Z - Y), P(Z + 1), P(Z - 1), P(-Z + 1), P(-Z - 1), omega,
+                              &out);
+#undef P
+        } else {
+            // bulk load: coefficients, then p in ascending address order
+            double cf[12];
+#pragma unroll
+            for (int a = 0; a < 12; ++a) cf[a] = c.f[a][q];
+            const long long off[19] = {-Z - Y, -Z - 1, -Z, -Z + 1, -Z + Y, -Y - 1, -Y, -Y + 1, -1, 0,
+                                       1,      Y - 1,  Y,  Y + 1,  Z - Y,  Z - 1,  Z,  Z + 1,  Z + Y};
+            double v[19];
+#pragma unroll
+            for (int t = 0; t < 19; ++t) v[t] = (double)p[q + off[t]];
+            // names by offset
+            const double mS = v[0], mW = v[1], pD = v[2], mE = v[3], mN = v[4], pSW = v[5], pS = v[6], pSE = v[7],
+                         pW = v[8], pc = v[9], pE = v[10], pNW = v[11], pN = v[12], pNE = v[13], uS = v[14],
+                         uW = v[15], pU = v[16], uE = v[17], uN = v[18];
+            if (FORM == FORM_BULK) {  // the plain arithmetic order
+                double s0 = cf[A0] * pE;
+                s0 = s0 + cf[A1] * pN;
+                s0 = s0 + cf[A2] * pU;
+                s0 = s0 + cf[B0] * (((pNE - pSE) - pNW) + pSW);
+                s0 = s0 + cf[B1] * (((uN - uS) - mN) + mS);
+                s0 = s0 + cf[B2] * (((uE - uW) - mE) + mW);
+                s0 = s0 + cf[C0] * pW;
+                s0 = s0 + cf[C1] * pS;
+                s0 = s0 + cf[C2] * pD;
+                s0 = s0 + cf[WRK1];
+                ss = (s0 * cf[A3] - pc) * cf[BND];
+                out = (float)(pc + omega * ss);
+            } else {
+                ss = p19_sat_math(cf, pc, pE, pW, pN, pS, pU, pD, pNE, pSE, pNW, pSW, uN, uS, mN, mS, uE, uW, mE, mW,
+                                  omega, &out);
+            }
+        }
+        pn[q] = out;
+        d2 = ss * ss;
+    }
+    if (part) {
+        __shared__ double lds[kMaxWaves];
+        const double s = block_sum_f64(d2, lds);
+        if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) part[block_linear_id()] = s;
+    }
+}
+
 template <int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void poisson19_sat(const float *__restrict__ p, float *__restrict__ pn,
                                                         P19Coef c, Geom g, double omega, int zb, int remap,
@@ -174,7 +268,7 @@ bool plain_tile_ok(Tile t) {
     X(128, 4) X(256, 1)
 
 bool p19_tile_ok(int v, Tile t) {
-    if (v == V_PLAIN) return plain_tile_ok(t);
+    if (v == V_PLAIN || v >= V_CSE_SAT) return plain_tile_ok(t);
     if (t.tz < 1) return false;
 #define X(a, b) if (t.tx == a && t.ty == b) return true;
     P19_SAT_TILES(X)
@@ -199,6 +293,13 @@ hipError_t p19_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
     dim3 grid(cdiv(a.g.nx, t.tx), cdiv(a.g.ny, t.ty), cdiv(a.g.nz, t.tz));
     if (v == V_PLAIN) {
         hipLaunchKernelGGL(poisson19_plain, grid, dim3(t.tx, t.ty, t.tz), 0, s, src, dst, c, a.g, a.omega, a.part);
+        return hipGetLastError();
+    }
+    if (v >= V_CSE_SAT) {
+        const dim3 blk(t.tx, t.ty, t.tz);
+        if (v == V_CSE_SAT) hipLaunchKernelGGL(poisson19_point<FORM_SAT>, grid, blk, 0, s, src, dst, c, a.g, a.omega, a.part);
+        else if (v == V_CSE_BULK) hipLaunchKernelGGL(poisson19_point<FORM_BULK>, grid, blk, 0, s, src, dst, c, a.g, a.omega, a.part);
+        else hipLaunchKernelGGL(poisson19_point<FORM_BOTH>, grid, blk, 0, s, src, dst, c, a.g, a.omega, a.part);
         return hipGetLastError();
     }
 #define X(A, B)                                                                                          \

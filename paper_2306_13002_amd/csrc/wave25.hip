@@ -81,6 +81,102 @@ __global__ void wave25_plain(const double *__restrict__ cur, double *__restrict_
     }
 }
 
+// Per-point forms of the paper's ablation (Sec. Evaluation: CSE, CSE+SAT,
+// CSE+BULK, ACCSAT), one thread per point with every operand from memory.
+// The plain body already loads each address once, so CSE is the plain form.
+//   FORM_SAT  : the rewritten arithmetic of the saturated form (3*c0 folded,
+//               taps grouped by radius, FMA chain), loads where first used;
+//   FORM_BULK : every load first, in ascending address order (previous level
+//               and vsq, then z-4 .. z+4 of u^n with each plane's taps by
+//               address), then the plain arithmetic order;
+//   FORM_BOTH : the loads of FORM_BULK, then the arithmetic of FORM_SAT.
+enum { FORM_SAT = 0, FORM_BULK = 1, FORM_BOTH = 2 };
+
+template <int FORM>
+__global__ void wave25_point(const double *__restrict__ cur, double *__restrict__ pn, const double *__restrict__ vsq,
+                             Geom g, W25C c, double *__restrict__ part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    double d2 = 0.0;
+    if (i < g.nx && j < g.ny && k < g.nz) {
+        const long long q = (long long)(k + 4) * g.pz + (long long)(j + 4) * g.py + (i + 4);
+        const long long Y = g.py, Z = g.pz;
+        double nv, u;
+        if (FORM == FORM_SAT) {
+            u = cur[q];
+            const double s1 = ((cur[q - 1] + cur[q + 1]) + (cur[q - Y] + cur[q + Y])) + (cur[q - Z] + cur[q + Z]);
+            const double s2 = ((cur[q - 2] + cur[q + 2]) + (cur[q - 2 * Y] + cur[q + 2 * Y])) +
+                              (cur[q - 2 * Z] + cur[q + 2 * Z]);
+            const double s3 = ((cur[q - 3] + cur[q + 3]) + (cur[q - 3 * Y] + cur[q + 3 * Y])) +
+                              (cur[q - 3 * Z] + cur[q + 3 * Z]);
+            const double s4 = ((cur[q - 4] + cur[q + 4]) + (cur[q - 4 * Y] + cur[q + 4 * Y])) +
+                              (cur[q - 4 * Z] + cur[q + 4 * Z]);
+            double L = c.c0x3 * u;
+            L = fma(c.c1, s1, L);
+            L = fma(c.c2, s2, L);
+            L = fma(c.c3, s3, L);
+            L = fma(c.c4, s4, L);
+            nv = fma(vsq[q], L, 2.0 * u - pn[q]);
+        } else {
+            // bulk load in ascending address order
+            const double up = pn[q], vv = vsq[q];
+            double zm[4], ym[4], xm[4], xp[4], yp[4], zp[4];
+#pragma unroll
+            for (int r = 4; r >= 1; --r) zm[r - 1] = cur[q - r * Z];
+#pragma unroll
+            for (int r = 4; r >= 1; --r) ym[r - 1] = cur[q - r * Y];
+#pragma unroll
+            for (int r = 4; r >= 1; --r) xm[r - 1] = cur[q - r];
+            u = cur[q];
+#pragma unroll
+            for (int r = 1; r <= 4; ++r) xp[r - 1] = cur[q + r];
+#pragma unroll
+            for (int r = 1; r <= 4; ++r) yp[r - 1] = cur[q + r * Y];
+#pragma unroll
+            for (int r = 1; r <= 4; ++r) zp[r - 1] = cur[q + r * Z];
+            const double cr[5] = {c.c0, c.c1, c.c2, c.c3, c.c4};
+            if (FORM == FORM_BULK) {  // the plain arithmetic order
+                double L = c.c0 * u;
+#pragma unroll
+                for (int r = 1; r <= 4; ++r) {
+                    L = L + cr[r] * xp[r - 1];
+                    L = L + cr[r] * xm[r - 1];
+                }
+                L = L + c.c0 * u;
+#pragma unroll
+                for (int r = 1; r <= 4; ++r) {
+                    L = L + cr[r] * yp[r - 1];
+                    L = L + cr[r] * ym[r - 1];
+                }
+                L = L + c.c0 * u;
+#pragma unroll
+                for (int r = 1; r <= 4; ++r) {
+                    L = L + cr[r] * zp[r - 1];
+                    L = L + cr[r] * zm[r - 1];
+                }
+                nv = (2.0 * u - up) + vv * L;
+            } else {  // the saturated arithmetic
+                double L = c.c0x3 * u;
+#pragma unroll
+                for (int r = 1; r <= 4; ++r) {
+                    const double sr = ((xm[r - 1] + xp[r - 1]) + (ym[r - 1] + yp[r - 1])) + (zm[r - 1] + zp[r - 1]);
+                    L = fma(cr[r], sr, L);
+                }
+                nv = fma(vv, L, 2.0 * u - up);
+            }
+        }
+        pn[q] = nv;
+        const double d = nv - u;
+        d2 = d * d;
+    }
+    if (part) {
+        __shared__ double lds[kMaxWaves];
+        const double s = block_sum_f64(d2, lds);
+        if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) part[block_linear_id()] = s;
+    }
+}
+
 template <int TX, int BY, int RY>
 __global__ __launch_bounds__(TX *BY) void wave25_sat(const double *__restrict__ cur, double *__restrict__ pn,
                                                      const double *__restrict__ vsq, Geom g, W25C c, int zb,
@@ -191,7 +287,7 @@ bool plain_tile_ok(Tile t) {
     X(32, 8, 8, 1) X(32, 16, 8, 2) X(128, 4, 4, 1) X(128, 8, 4, 2) X(128, 8, 8, 1) X(256, 4, 4, 1)
 
 bool w25_tile_ok(int v, Tile t) {
-    if (v == V_PLAIN) return plain_tile_ok(t);
+    if (v == V_PLAIN || v >= V_CSE_SAT) return plain_tile_ok(t);
     if (t.tz < 1) return false;
 #define X(A_, TY_, BY_, RY_) if (t.tx == A_ && t.ty == TY_) return true;
     W25_SAT_TILES(X)
@@ -217,6 +313,13 @@ hipError_t w25_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
     dim3 grid(cdiv(a.g.nx, t.tx), cdiv(a.g.ny, t.ty), cdiv(a.g.nz, t.tz));
     if (v == V_PLAIN) {
         hipLaunchKernelGGL(wave25_plain, grid, dim3(t.tx, t.ty, t.tz), 0, s, cur, pn, vsq, a.g, c, a.part);
+        return hipGetLastError();
+    }
+    if (v >= V_CSE_SAT) {
+        const dim3 blk(t.tx, t.ty, t.tz);
+        if (v == V_CSE_SAT) hipLaunchKernelGGL(wave25_point<FORM_SAT>, grid, blk, 0, s, cur, pn, vsq, a.g, c, a.part);
+        else if (v == V_CSE_BULK) hipLaunchKernelGGL(wave25_point<FORM_BULK>, grid, blk, 0, s, cur, pn, vsq, a.g, c, a.part);
+        else hipLaunchKernelGGL(wave25_point<FORM_BOTH>, grid, blk, 0, s, cur, pn, vsq, a.g, c, a.part);
         return hipGetLastError();
     }
 #define X(A, TY, BY, RY)                                                                                   \

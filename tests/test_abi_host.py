@@ -79,3 +79,10 @@ def test_null_arguments():
     assert L.stencil_destroy(None) == S.OK
     assert isinstance(S.last_error(), str)
     assert L.stencil_version().decode().endswith("gfx950")
+
+
+def test_ablation_forms_only_for_wave_and_pressure():
+    d, keep = S.make_desc("heat3d7", (10, 10, 10), coef=(0.4, 0.1), variant="cse_sat")
+    assert S.plan_status(d)[0] == S.E_UNSUPPORTED and "ablation" in S.last_error()
+    d, keep = S.make_desc("wave25", (10, 10, 10), coef=(1, 2, 3, 4, 5), variant="cse_bulk")
+    assert S.plan_status(d)[0] in (S.OK, S.E_DEVICE)
