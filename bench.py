@@ -54,12 +54,14 @@ def read_traffic(kernel_tag: str, source: str):
         return None
 
 
-def setup_workload(name, variant, dev, torch, synth, Plan):
-    """Returns (plan, run_step, points_per_step, sweeps_per_step, meta)."""
+def setup_workload(name, variant, dev, torch, synth, Plan, plan_kw=None):
+    """Returns (plan, run_step, reset, points_per_step, sweeps_per_step, meta)."""
+    pk = dict(tune=TUNE)
+    pk.update(plan_kw or {})
     if name == "poisson19":
         p0, cf = synth.poisson19_inputs()
         n = (127, 127, 255)
-        plan = Plan("poisson19", n, variant=variant, omega=0.8, tune=TUNE)
+        plan = Plan("poisson19", n, variant=variant, omega=0.8, **pk)
         f = [torch.tensor(p0, device=dev), torch.empty(p0.shape, dtype=torch.float32, device=dev)]
         cs = [torch.tensor(c, device=dev) for c in cf]
         base = f[0].clone()
@@ -81,7 +83,7 @@ def setup_workload(name, variant, dev, torch, synth, Plan):
     if name == "wave25":
         a, b, v = synth.wave25_inputs(512)
         n = (512, 512, 512)
-        plan = Plan("wave25", n, variant=variant, coef=synth.WAVE25_COEF, tune=TUNE)
+        plan = Plan("wave25", n, variant=variant, coef=synth.WAVE25_COEF, **pk)
         f = [torch.tensor(a, device=dev), torch.tensor(b, device=dev)]
         vs = [torch.tensor(v, device=dev)]
         del a, b, v
@@ -204,8 +206,8 @@ def setup_workload(name, variant, dev, torch, synth, Plan):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_variant(name, variant, steps, warmup, dev, torch, synth, Plan):
-    plan, step, reset, pts, T, meta = setup_workload(name, variant, dev, torch, synth, Plan)
+def time_variant(name, variant, steps, warmup, dev, torch, synth, Plan, plan_kw=None):
+    plan, step, reset, pts, T, meta = setup_workload(name, variant, dev, torch, synth, Plan, plan_kw)
     plan.profile(True)
     for _ in range(warmup):
         reset()
@@ -347,6 +349,16 @@ def main():
                         "achieved_gbs": alg_bytes / pl / 1e9, "avg_launch_us": pl * 1e6,
                         "tile": list(pr["cfg"]["tile"]), "tile_map": pr["cfg"].get("tile_map")}
         out["saturated_over_plain"] = value / pv
+        if a.workload in ("poisson19", "wave25"):
+            # the paper's ablation forms (per point), at the plain form's tuned shape
+            abl = {"plain": {"us_per_sweep": pl * 1e6}, "saturated": {"us_per_sweep": launch_s * 1e6}}
+            for form in ("cse_sat", "cse_bulk", "accsat_point"):
+                fr = time_variant(a.workload, form, max(2, a.steps // 4), 2, dev, torch, synth, Plan,
+                                  dict(tune="fixed", tile=tuple(pr["cfg"]["tile"])))
+                abl[form] = {"us_per_sweep": fr["sweep_ms"] / 1000.0 / max(1, fr["sweeps"]) * 1e6}
+            for v in abl.values():
+                v["algorithmic_gbs"] = alg_bytes / (v["us_per_sweep"] * 1e-6) / 1e9
+            out["ablation"] = abl
     if not a.no_cpu and a.workload not in ("copy", "batch"):
         out["cpu_baseline"] = cpu_baseline(a.workload)
     print(json.dumps(out), flush=True)
