@@ -234,6 +234,14 @@ stencil_status stencil_mlp_train(const float *X, const float *y, int32_t n, cons
  * host out).  Synchronizes `stream`. */
 stencil_status stencil_mlp_predict(const float *model, const float *X, int32_t n, float *y_out, void *stream);
 
+/* GENERIC saturated plans run kernels generated for their taps and compiled
+ * with hipRTC when the plan is made (one per tile shape; cached per process
+ * and, if STENCIL_RTC_CACHE names a directory, as code objects there;
+ * STENCIL_GENERIC_TABLE=1 selects the precompiled table-driven kernel).
+ * stencil_prepare compiles, concurrently, every generated kernel the tuners
+ * may try for d so later plans find them cached.  Other kinds: no-op. */
+stencil_status stencil_prepare(const stencil_desc *d);
+
 /* Release a plan and its buffers (waits for nothing; the caller must not
  * destroy a plan while its work is in flight).  NULL is accepted. */
 stencil_status stencil_destroy(stencil_plan_t p);

@@ -94,6 +94,7 @@ def collect(out, names):
         kind, n, kw = stencil_spec(name)
         fields, coefs = device_inputs(name, kind, n, kw, torch, dev)
         cands = S.candidates(kind, n, **kw)
+        S.prepare(kind, n, **kw)  # compiles generated kernels in parallel, before any timing
         X = np.stack([S.features(kind, n, c, **kw) for c in cands])
         secs = np.array([time_candidate(kind, n, kw, c, fields, coefs, torch) for c in cands])
         np.savez(path, X=X, y=np.log(secs), secs=secs,

@@ -20,6 +20,7 @@
 #include "internal.hpp"
 #include "plan.hpp"
 #include "tune.hpp"
+#include "rtc.hpp"
 
 using namespace stn;
 
@@ -153,6 +154,26 @@ stencil_status build_generic_tables(stencil_plan_s *p, const stencil_desc *d) {
     t.corners = false;
     for (int k = 0; k < n; ++k)
         if (d->tap_off[3 * k] != 0 && d->tap_off[3 * k + 1] != 0) t.corners = true;
+    // the same grouping, for the generated saturated kernels
+    RtcSpec *sp = new (std::nothrow) RtcSpec();
+    if (!sp) return fail(STENCIL_E_NOMEM, "host allocation failed");
+    sp->R = r;
+    sp->eb = elem_bytes(d->dtype);
+    sp->corners = t.corners;
+    sp->slots.resize(ns);
+    for (int s = 0; s < ns; ++s)
+        for (int gi = slot_g[s]; gi < slot_g[s + 1]; ++gi) {
+            RtcGroup gr;
+            gr.coef = g_c[gi];
+            for (int ti = g_t[gi]; ti < g_t[gi + 1]; ++ti) {
+                const int xy = t_xy[ti];
+                gr.taps.push_back({(short)(xy & 0xFFFF), xy >> 16});
+            }
+            sp->slots[s].push_back(gr);
+        }
+    p->rtc = sp;
+    const char *tbl = std::getenv("STENCIL_GENERIC_TABLE");
+    p->base_args.rtc = (tbl && std::atoi(tbl) != 0) ? nullptr : sp;
     return STENCIL_OK;
 }
 
@@ -266,6 +287,7 @@ void free_plan(stencil_plan_s *p) {
     if (p->d_red) (void)hipFree(p->d_red);
     if (p->d_tab) (void)hipFree(p->d_tab);
     free_batch(p->batch);
+    delete p->rtc;
     if (p->d_result) (void)hipFree(p->d_result);
     if (p->h_result) (void)hipHostFree(p->h_result);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
@@ -381,6 +403,11 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out) {
     if ((st = choose_config(p, d)) != STENCIL_OK || (st = alloc_plan_buffers(p)) != STENCIL_OK) {
         free_plan(p);
         return st;
+    }
+    if (p->kind == STENCIL_GENERIC && p->variant == V_SATURATED && p->base_args.rtc &&
+        !rtc_prepare(*p->rtc, {p->tile})) {
+        logf("%s; using the table-driven generic kernel", stencil_last_error());
+        p->base_args.rtc = nullptr;
     }
     logf("plan kind=%d variant=%d tile=(%d,%d,%d) map=%d tuned=%d n=(%d,%d,%d) blocks=%lld", p->kind, p->variant,
          p->tile.tx, p->tile.ty, p->tile.tz, p->remap ? 2 : 1, (int)p->tuned, g.nx, g.ny, g.nz, p->nblocks);
@@ -513,6 +540,35 @@ stencil_status stencil_profile_read(stencil_plan_t p, double *sweep_ms, int32_t 
     *sweep_ms = ms;
     if (sweeps) *sweeps = p->prof_sweeps;
     return STENCIL_OK;
+}
+
+stencil_status stencil_prepare(const stencil_desc *d) {
+    if (!d) return fail(STENCIL_E_INVAL, "descriptor is NULL");
+    Geom g{};
+    int rz = 0;
+    stencil_status st = validate_desc(d, g, rz);
+    if (st != STENCIL_OK || d->kind != STENCIL_GENERIC) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(STENCIL_E_DEVICE, "no HIP device available");
+    stencil_plan_s tmp;
+    tmp.kind = d->kind;
+    tmp.dtype = d->dtype;
+    tmp.g = g;
+    tmp.rz = rz;
+    tmp.base_args.g = g;
+    tmp.base_args.elem_bytes = elem_bytes(d->dtype);
+    if ((st = build_generic_tables(&tmp, d)) != STENCIL_OK) {
+        if (tmp.d_tab) (void)hipFree(tmp.d_tab);
+        delete tmp.rtc;
+        return st;
+    }
+    TuneRequest rq{STENCIL_SATURATED, d->tile_x, d->tile_y, d->zblock, d->tile_map};
+    std::vector<Tile> tiles;
+    for (const Cand &c : tune_candidates(&generic_ops, STENCIL_GENERIC, g, rq)) tiles.push_back(c.tile);
+    const bool ok = rtc_prepare(*tmp.rtc, tiles);
+    (void)hipFree(tmp.d_tab);
+    delete tmp.rtc;
+    return ok ? STENCIL_OK : STENCIL_E_DEVICE;
 }
 
 stencil_status stencil_destroy(stencil_plan_t p) {

@@ -4,9 +4,11 @@
 // (k+r)*pz + (j+r)*py + (i+r) elements from the base pointer.
 #pragma once
 
+#if !defined(__HIPCC_RTC__)  // hipRTC (generated kernels) provides the runtime itself
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#endif
 
 namespace stn {
 

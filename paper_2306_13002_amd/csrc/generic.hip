@@ -19,7 +19,9 @@
 // wait in a register queue of FP64 accumulators (plane accumulation), so
 // every input value is read from memory once per block.  The next plane's
 // loads are issued before the current plane's arithmetic.
+#include "generic_body.hpp"
 #include "internal.hpp"
+#include "rtc.hpp"
 
 namespace stn {
 namespace {
@@ -49,68 +51,14 @@ __global__ void generic_plain(const T *__restrict__ src, T *__restrict__ dst, Ge
     }
 }
 
+// Table-driven tap sums: slot s's groups are read from the plan's tables.
 template <typename T, int R, int TX, int TY, bool CORNERS>
-__global__ __launch_bounds__(TX *TY) void generic_sat(const T *__restrict__ src, T *__restrict__ dst, Geom g,
-                                                      GenTab tab, int zb, int remap, double *__restrict__ part) {
-    constexpr int W = TX + 2 * R, NT = TX * TY, PLANE = (TY + 2 * R) * W, NQ = 2 * R + 1;
-    __shared__ double tile[2][PLANE];
-    __shared__ double red[kMaxWaves];
-    int bx, by, bz;
-    tile_coords(remap, bx, by, bz);
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-    const int i = bx * TX + tx, j = by * TY + ty;
-    const int xp = i + R, yp = j + R;
-    const int PX = g.nx + 2 * R, PY = g.ny + 2 * R;
-    const bool in = i < g.nx && j < g.ny;
-    const bool ld = xp < PX && yp < PY;
-    const int k0 = bz * zb, k1 = min(k0 + zb, g.nz);
-    const long long col = (long long)yp * g.py + xp;
-    const int me = (ty + R) * W + (tx + R);
-
-    HaloStager<T, TX, TY, R, CORNERS, NT> halo;
-    halo.init(tid, bx * TX + R, by * TY + R, g.py, PX, PY);
-
-    // acc[s]: output plane m + R - s after input plane m; ctr[s]: that
-    // output's old value (for the residual)
-    double acc[NQ], ctr[NQ];
+struct TableSlotsW {
+    GenTab tab;
+    __device__ __forceinline__ void operator()(const double *__restrict__ t, int me, double *acc) const {
+        constexpr int W = TX + 2 * R;
 #pragma unroll
-    for (int s = 0; s < NQ; ++s) {
-        acc[s] = 0.0;
-        ctr[s] = 0.0;
-    }
-    // input planes m = k0-R .. k1-1+R  (padded z = m + R)
-    int zp = k0;
-    T cval = ld ? src[col + (long long)zp * g.pz] : T(0);
-    halo.load(src + (long long)zp * g.pz);
-    double sacc = 0.0;
-    const int zend = k1 - 1 + 2 * R;
-    for (int b = 0; zp <= zend; ++zp, b ^= 1) {
-        double *t = tile[b];
-        t[me] = (double)cval;
-#pragma unroll
-        for (int s = 0; s < decltype(halo)::HR; ++s)
-            if (halo.has[s]) t[halo.lidx[s]] = (double)halo.val[s];
-        const double cur_ctr = (double)cval;
-        if (zp < zend) {  // bulk load of the next plane
-            cval = ld ? src[col + (long long)(zp + 1) * g.pz] : T(0);
-            halo.load(src + (long long)(zp + 1) * g.pz);
-        }
-        __syncthreads();
-        // shift the queues (input plane m = zp - R): slot s now holds output
-        // plane m + R - s, slot 0 starts empty
-#pragma unroll
-        for (int s = NQ - 1; s > 0; --s) {
-            acc[s] = acc[s - 1];
-            ctr[s] = ctr[s - 1];
-        }
-        acc[0] = 0.0;
-        ctr[0] = 0.0;
-        // the centre value of this input plane is the old value of output m,
-        // which sits in slot R after the shift
-        ctr[R] = cur_ctr;
-#pragma unroll
-        for (int s = 0; s < NQ; ++s) {
-            // slot s receives taps with dz = s - R
+        for (int s = 0; s < 2 * R + 1; ++s) {
             const int g0 = tab.slot_g[s], g1 = tab.slot_g[s + 1];
             double a = acc[s];
             for (int gi = g0; gi < g1; ++gi) {
@@ -139,18 +87,21 @@ __global__ __launch_bounds__(TX *TY) void generic_sat(const T *__restrict__ src,
             }
             acc[s] = a;
         }
-        // output m - R (slot 2R) is complete
-        const int kout = zp - 2 * R;  // interior index of output m - R (m = zp - R)
-        if (in && kout >= k0 && kout < k1) {
-            const T out = (T)acc[2 * R];
-            dst[col + (long long)(kout + R) * g.pz] = out;
-            const double d = (double)out - ctr[2 * R];
-            sacc = fma(d, d, sacc);
-        }
     }
+};
+
+template <typename T, int R, int TX, int TY, bool CORNERS>
+__global__ __launch_bounds__(TX *TY) void generic_sat(const T *__restrict__ src, T *__restrict__ dst, Geom g,
+                                                      GenTab tab, int zb, int remap, double *__restrict__ part) {
+    __shared__ double tile[2][(TY + 2 * R) * (TX + 2 * R)];
+    __shared__ double red[kMaxWaves];
+    int bx, by, bz;
+    tile_coords(remap, bx, by, bz);
+    const double sacc = generic_sat_body<T, R, TX, TY, CORNERS>(src, dst, g, zb, bx, by, bz,
+                                                               TableSlotsW<T, R, TX, TY, CORNERS>{tab}, tile);
     if (part) {
         const double s = block_sum_f64(sacc, red);
-        if (tid == 0) part[block_linear_id()] = s;
+        if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = s;
     }
 }
 
@@ -159,7 +110,7 @@ bool plain_tile_ok(Tile t) {
     return t.tx >= 1 && t.ty >= 1 && t.tz >= 1 && n % 64 == 0 && n <= 1024;
 }
 
-#define GEN_SAT_TILES(X) X(32, 2) X(32, 4) X(32, 8) X(64, 1) X(64, 2) X(64, 4) X(128, 1) X(128, 2)
+#define GEN_SAT_TILES(X) X(32, 4) X(32, 8) X(64, 2) X(64, 4) X(128, 2)
 
 bool gen_tile_ok(int v, Tile t) {
     if (v == V_PLAIN) return plain_tile_ok(t);
@@ -211,6 +162,7 @@ hipError_t gen_launch_t(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 }
 
 hipError_t gen_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
+    if (v == V_SATURATED && a.rtc) return rtc_generic_launch(*a.rtc, t, a, s);
     return a.elem_bytes == 4 ? gen_launch_t<float>(v, t, a, s) : gen_launch_t<double>(v, t, a, s);
 }
 

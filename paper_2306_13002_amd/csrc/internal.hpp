@@ -18,6 +18,8 @@ struct Tile {
     int tx, ty, tz;
 };
 
+struct RtcSpec;  // generated saturated generic kernels (rtc.hpp)
+
 // GENERIC tap tables (device pointers, uniform over a launch).
 struct GenTab {
     const int *off;     // plain: linear offset dz*pz + dy*py + dx per tap, caller's order
@@ -45,6 +47,7 @@ struct SweepArgs {
     int remap;                // saturated forms: XCD-chunked block -> tile map (1) or natural order (0)
     GenTab gen;               // GENERIC tap tables
     int elem_bytes;           // storage size (GENERIC: 4 or 8)
+    const RtcSpec *rtc;       // GENERIC saturated: generated kernels (nullptr: table-driven kernel)
 };
 
 // Batched runs: one problem of a batch and one work item (a tile of a

@@ -6,6 +6,7 @@
 #include "../../include/stencil.h"
 #include "internal.hpp"
 #include "tune.hpp"
+#include "rtc.hpp"
 
 #include <vector>
 
@@ -57,6 +58,7 @@ struct stencil_plan_s {
     stn::SweepArgs base_args{};  // geometry and scalars shared by every launch of this plan
     unsigned taps_hash = 0;      // GENERIC: hash of the tap pattern (part of the tune key)
     void *d_tab = nullptr;       // GENERIC: device tap tables
+    stn::RtcSpec *rtc = nullptr; // GENERIC: spec of the generated saturated kernels
     bool tuned = false;          // configuration came from the autotuner
     BatchState *batch = nullptr; // non-null for plans made by stencil_plan_batch
     stn::StencilInfo info{};     // static description (cost-model features)

@@ -1,0 +1,31 @@
+// rtc.hpp -- generated saturated generic kernels (hipRTC), see rtc.cpp.
+#pragma once
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace stn {
+
+// One coefficient group of one z slot: coefficient and its taps (dx, dy),
+// in ascending address order.
+struct RtcGroup {
+    double coef;
+    std::vector<std::pair<int, int>> taps;
+};
+
+// What a generated kernel depends on besides its tile.
+struct RtcSpec {
+    int R = 1, eb = 8;
+    bool corners = false;
+    std::vector<std::vector<RtcGroup>> slots;  // 2R+1 slots, slot s holds dz = s - R
+};
+
+std::string rtc_generic_source(const RtcSpec &sp, int TX, int TY);
+// Compile the generated kernels of the given tiles (concurrently); false if any failed.
+bool rtc_prepare(const RtcSpec &sp, const std::vector<Tile> &tiles);
+hipError_t rtc_generic_launch(const RtcSpec &sp, Tile t, const SweepArgs &a, hipStream_t s);
+
+}  // namespace stn

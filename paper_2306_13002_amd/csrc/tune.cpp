@@ -22,6 +22,7 @@
 #include "internal.hpp"
 #include "plan.hpp"
 #include "tune.hpp"
+#include "rtc.hpp"
 
 namespace stn {
 
@@ -182,6 +183,15 @@ static double time_one(const stencil_plan_s *p, const Cand &c, Buffers &b, hipSt
 stencil_status tune_exhaustive(stencil_plan_s *p, const TuneRequest &rq, TuneEntry *best) {
     const std::vector<Cand> cands = tune_candidates(p->ops, p->kind, p->g, rq);
     if (cands.empty()) return fail(STENCIL_E_UNSUPPORTED, "no launch shape matches the requested tile fields");
+    if (p->kind == STENCIL_GENERIC && p->base_args.rtc) {  // compile the generated kernels up front, in parallel
+        std::vector<Tile> tiles;
+        for (const Cand &c : cands)
+            if (c.variant == V_SATURATED) tiles.push_back(c.tile);
+        if (!tiles.empty() && !rtc_prepare(*p->rtc, tiles)) {
+            logf("%s; tuning the table-driven generic kernel", stencil_last_error());
+            p->base_args.rtc = nullptr;
+        }
+    }
     const int eb = elem_bytes(p->dtype);
     const long long span = (long long)(p->g.PZ() - 1) * p->g.pz * (p->rz ? 1 : 0) +
                            (long long)(p->g.PY() - 1) * p->g.py + p->g.PX();

@@ -80,6 +80,8 @@ def lib():
         L.stencil_features.argtypes = [ctypes.POINTER(StencilDesc), i32, i32, i32, i32, i32, fp]
         L.stencil_mlp_train.argtypes = [fp, fp, i32, fp, i32, ctypes.c_float, fp, fp, vp]
         L.stencil_mlp_predict.argtypes = [fp, fp, i32, fp, vp]
+        L.stencil_prepare.argtypes = [ctypes.POINTER(StencilDesc)]
+        L.stencil_prepare.restype = ctypes.c_int
         for f in (L.stencil_plan, L.stencil_run, L.stencil_residual, L.stencil_plan_config,
                   L.stencil_profile_enable, L.stencil_profile_read, L.stencil_destroy, L.stencil_plan_batch,
                   L.stencil_residuals, L.stencil_candidates, L.stencil_features, L.stencil_mlp_train,
@@ -357,6 +359,12 @@ def candidates(kind: str, n, **kw):
         v, tx, ty, zb, m = buf[5 * i:5 * i + 5]
         out.append((VARIANT_NAMES[v], (tx, ty, zb), TILE_MAP_NAMES[m]))
     return out
+
+
+def prepare(kind: str, n, **kw):
+    """Compile the generated kernels the tuners may try (GENERIC; else no-op)."""
+    d, keep = make_desc(kind, n, **kw)
+    _check(lib().stencil_prepare(ctypes.byref(d)))
 
 
 def features(kind: str, n, cand, **kw):
