@@ -245,7 +245,7 @@ def cpu_baseline(name):
         t = time.perf_counter()
         oracle.poisson19(p0, cf, 0.8, 2, mode="F32STORE")
         one = (time.perf_counter() - t) / 2
-        k = max(2, min(2000, int(10.0 / max(one, 1e-3))))
+        k = max(2, min(4000, int(25.0 / max(one, 1e-3))))
         t = time.perf_counter()
         oracle.poisson19(p0, cf, 0.8, k, mode="F32STORE")
         dt = time.perf_counter() - t
