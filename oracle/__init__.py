@@ -48,7 +48,10 @@ def _load():
         lib.oracle_generic_run.argtypes = [i64, i64, i64, cint, dp, cint,
                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                            dp, cint, cint, cint, dp]
-        for f in (lib.oracle_heat_run, lib.oracle_poisson19_run, lib.oracle_wave25_run, lib.oracle_generic_run):
+        lib.oracle_program_run.argtypes = [i64, i64, i64, cint, ctypes.POINTER(ctypes.c_int32), cint, dp, cint, cint,
+                                           ctypes.POINTER(dp), cint, ctypes.POINTER(dp), cint, dp, cint]
+        for f in (lib.oracle_heat_run, lib.oracle_poisson19_run, lib.oracle_wave25_run, lib.oracle_generic_run,
+                  lib.oracle_program_run):
             f.restype = cint
         _lib = lib
     return _lib
@@ -149,3 +152,31 @@ def generic(u, radius: int, tap_off, tap_cid, coef, T: int, mode: str = "F64"):
                                       cid.ctypes.data_as(i32p), _ptr(cf), int(cf.shape[0]), int(T), m,
                                       ctypes.byref(res)), "generic")
     return a, res.value
+
+
+def program(prog: dict, inputs, params, n):
+    """Run a pointwise program once (see oracle_program_run in oracle.c).
+
+    prog: dict with n_inputs, n_outputs, n_params, n_locals, radius, insns
+    (list of (op, a, b, c, d)) and consts; inputs: padded 3-D arrays (halo
+    radius); params: n_params floats; n: interior (nx, ny, nz).  Returns the
+    n_outputs padded output arrays (halo 0, interior written)."""
+    r = int(prog["radius"])
+    nx, ny, nz = (int(v) for v in n)
+    shape = (nz + 2 * r, ny + 2 * r, nx + 2 * r)
+    ins = [_f64(a) for a in inputs]
+    for a in ins:
+        if a.shape != shape:
+            raise ValueError("program: input shape does not match n and radius")
+    outs = [np.zeros(shape, dtype=np.float64) for _ in range(int(prog["n_outputs"]))]
+    code = np.ascontiguousarray(np.asarray(prog["insns"], dtype=np.int32).reshape(-1, 5))
+    cs = np.ascontiguousarray(np.asarray(list(prog["consts"]) + [0.0], dtype=np.float64))
+    pr = np.ascontiguousarray(np.asarray(list(params) + [0.0], dtype=np.float64))
+    dp = ctypes.POINTER(ctypes.c_double)
+    in_arr = (dp * max(1, len(ins)))(*[_ptr(a) for a in ins])
+    out_arr = (dp * len(outs))(*[_ptr(a) for a in outs])
+    _check(_load().oracle_program_run(nx, ny, nz, r, code.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      int(code.shape[0]), _ptr(cs), len(prog["consts"]), len(ins), in_arr,
+                                      len(outs), out_arr, int(prog["n_params"]), _ptr(pr), int(prog["n_locals"])),
+           "program")
+    return outs

@@ -316,3 +316,82 @@ int oracle_generic_run(int64_t nx, int64_t ny, int64_t nz, int r, double *u, int
     if (resid) *resid = rs;
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/*
+ * Pointwise multi-statement program (the loop body the paper rewrites, Sec.
+ * "E-Graph Creation": straight-line assignments inside the innermost
+ * parallel loop).  For every interior point, in z, y, x order, the
+ * statements run in program order; each statement's expression is given in
+ * postfix form and evaluated with a value stack, one IEEE operation per
+ * instruction (so products and sums round in the written order):
+ *   op 1 CONST a      push consts[a]
+ *   op 2 PARAM a      push params[a]
+ *   op 3 LOAD a,b,c,d push in[a] at (i+b, j+c, k+d)
+ *   op 4 ADD, 5 SUB, 6 MUL: pop y, pop x, push x+y / x-y / x*y
+ *   op 7 NEG          pop x, push -x
+ *   op 8 STORE a      pop x, out[a] at (i,j,k) = x
+ *   op 9 SET a        pop x, local a = x
+ *   op 10 GET a       push local a
+ * insns: n_insns groups of 5 int32 (op, a, b, c, d).  Every array is a
+ * padded grid of this file's layout with halo r; outputs are written at
+ * interior points only.  Returns -1 on a malformed program.
+ */
+int oracle_program_run(int64_t nx, int64_t ny, int64_t nz, int r, const int32_t *insns, int n_insns,
+                       const double *consts, int n_consts, int n_in, const double *const *in, int n_out,
+                       double *const *out, int n_par, const double *params, int n_loc) {
+    if (!insns || n_insns < 1 || nx < 1 || ny < 1 || nz < 1 || r < 0 || n_in < 0 || n_out < 1 || n_par < 0 ||
+        n_loc < 0 || (n_in > 0 && !in) || !out || (n_par > 0 && !params) || (n_consts > 0 && !consts))
+        return -1;
+    /* check the program once: operand ranges and stack depth */
+    int depth = 0, max_depth = 0;
+    for (int q = 0; q < n_insns; ++q) {
+        const int32_t *s = insns + 5 * q;
+        switch (s[0]) {
+        case 1: if (s[1] < 0 || s[1] >= n_consts) return -1; ++depth; break;
+        case 2: if (s[1] < 0 || s[1] >= n_par) return -1; ++depth; break;
+        case 3:
+            if (s[1] < 0 || s[1] >= n_in) return -1;
+            for (int d = 2; d < 5; ++d)
+                if (s[d] < -r || s[d] > r) return -1;
+            ++depth;
+            break;
+        case 4: case 5: case 6: if (depth < 2) return -1; --depth; break;
+        case 7: if (depth < 1) return -1; break;
+        case 8: if (depth != 1 || s[1] < 0 || s[1] >= n_out) return -1; depth = 0; break;
+        case 9: if (depth != 1 || s[1] < 0 || s[1] >= n_loc) return -1; depth = 0; break;
+        case 10: if (s[1] < 0 || s[1] >= n_loc) return -1; ++depth; break;
+        default: return -1;
+        }
+        if (depth > max_depth) max_depth = depth;
+    }
+    if (depth != 0) return -1;
+    const int64_t PX = nx + 2 * r, PY = ny + 2 * r;
+    double *stack = (double *)malloc(sizeof(double) * (size_t)(max_depth + 1));
+    double *loc = (double *)calloc((size_t)(n_loc + 1), sizeof(double));
+    if (!stack || !loc) { free(stack); free(loc); return -1; }
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                const int64_t x = i + r, y = j + r, z = k + r;
+                int sp = 0;
+                for (int q = 0; q < n_insns; ++q) {
+                    const int32_t *s = insns + 5 * q;
+                    switch (s[0]) {
+                    case 1: stack[sp++] = consts[s[1]]; break;
+                    case 2: stack[sp++] = params[s[1]]; break;
+                    case 3: stack[sp++] = in[s[1]][PIDX(x + s[2], y + s[3], z + s[4], PX, PY)]; break;
+                    case 4: --sp; stack[sp - 1] = stack[sp - 1] + stack[sp]; break;
+                    case 5: --sp; stack[sp - 1] = stack[sp - 1] - stack[sp]; break;
+                    case 6: --sp; stack[sp - 1] = stack[sp - 1] * stack[sp]; break;
+                    case 7: stack[sp - 1] = -stack[sp - 1]; break;
+                    case 8: out[s[1]][PIDX(x, y, z, PX, PY)] = stack[--sp]; break;
+                    case 9: loc[s[1]] = stack[--sp]; break;
+                    case 10: stack[sp++] = loc[s[1]]; break;
+                    }
+                }
+            }
+    free(stack);
+    free(loc);
+    return 0;
+}

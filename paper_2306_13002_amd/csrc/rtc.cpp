@@ -9,7 +9,8 @@
 // literals, wrapped around the streaming body every generic kernel shares
 // (generic_body.hpp), and compiled for the device.  Modules are cached per
 // source text in-process and, when STENCIL_RTC_CACHE names a directory, as
-// code-object files there.
+// code-object files there.  rtc_function serves every generated kernel of
+// the library (also the saturator's programs).
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
@@ -36,7 +37,7 @@ void logf(const char *fmt, ...);
 namespace {
 
 std::mutex g_mu;
-std::map<std::string, hipFunction_t> g_fn;  // source hash + device -> kernel
+std::map<std::string, hipFunction_t> g_fn;  // hash of source and kernel name + device -> kernel
 
 unsigned long long fnv64(const std::string &s) {
     unsigned long long h = 1469598103934665603ull;
@@ -97,14 +98,13 @@ std::string rtc_generic_source(const RtcSpec &sp, int TX, int TY) {
     return o;
 }
 
-// Compile (or fetch) the generated kernel for one tile; returns nullptr and
-// sets the error text on failure.
-static hipFunction_t get_kernel(const RtcSpec &sp, int TX, int TY) {
+// Compile (or fetch from the caches) kernel `kernel` of source `src`;
+// returns nullptr and sets the error text on failure.
+hipFunction_t rtc_function(const std::string &src, const char *kernel) {
     int dev = 0;
     (void)hipGetDevice(&dev);
-    const std::string src = rtc_generic_source(sp, TX, TY);
-    char key[64];
-    std::snprintf(key, sizeof key, "%016llx-%d", fnv64(src), dev);
+    char key[96];
+    std::snprintf(key, sizeof key, "%016llx-%d", fnv64(src + '\n' + kernel), dev);
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_fn.find(key);
@@ -128,7 +128,7 @@ static hipFunction_t get_kernel(const RtcSpec &sp, int TX, int TY) {
         hiprtcProgram prog;
         const char *hdrs[] = {kCommonHppText, kGenericBodyHppText};
         const char *names[] = {"common.hpp", "generic_body.hpp"};
-        if (hiprtcCreateProgram(&prog, src.c_str(), "stencil_generic_gen.hip", 2, hdrs, names) != HIPRTC_SUCCESS) {
+        if (hiprtcCreateProgram(&prog, src.c_str(), "generated.hip", 2, hdrs, names) != HIPRTC_SUCCESS) {
             fail(STENCIL_E_DEVICE, "hiprtcCreateProgram failed");
             return nullptr;
         }
@@ -140,7 +140,7 @@ static hipFunction_t get_kernel(const RtcSpec &sp, int TX, int TY) {
             hiprtcGetProgramLogSize(prog, &ln);
             std::string log(ln + 1, '\0');
             hiprtcGetProgramLog(prog, &log[0]);
-            fail(STENCIL_E_DEVICE, "hipRTC compile of a generated generic kernel failed: %.400s", log.c_str());
+            fail(STENCIL_E_DEVICE, "hipRTC compile of generated kernel %s failed: %.400s", kernel, log.c_str());
             hiprtcDestroyProgram(&prog);
             return nullptr;
         }
@@ -158,9 +158,9 @@ static hipFunction_t get_kernel(const RtcSpec &sp, int TX, int TY) {
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;
     hipError_t e = hipModuleLoadData(&mod, code.data());
-    if (e == hipSuccess) e = hipModuleGetFunction(&fn, mod, "stencil_generic_gen");
+    if (e == hipSuccess) e = hipModuleGetFunction(&fn, mod, kernel);
     if (e != hipSuccess) {
-        fail(STENCIL_E_DEVICE, "loading a generated generic kernel: %s", hipGetErrorString(e));
+        fail(STENCIL_E_DEVICE, "loading generated kernel %s: %s", kernel, hipGetErrorString(e));
         return nullptr;
     }
     std::lock_guard<std::mutex> lk(g_mu);
@@ -168,6 +168,10 @@ static hipFunction_t get_kernel(const RtcSpec &sp, int TX, int TY) {
     if (it != g_fn.end()) return it->second;  // another thread won; its module stays loaded too
     g_fn[key] = fn;
     return fn;
+}
+
+static hipFunction_t get_kernel(const RtcSpec &sp, int TX, int TY) {
+    return rtc_function(rtc_generic_source(sp, TX, TY), "stencil_generic_gen");
 }
 
 bool rtc_prepare(const RtcSpec &sp, const std::vector<Tile> &tiles) {

@@ -23,6 +23,10 @@ struct RtcSpec {
     std::vector<std::vector<RtcGroup>> slots;  // 2R+1 slots, slot s holds dz = s - R
 };
 
+// Compile (or fetch from the in-process and STENCIL_RTC_CACHE caches) kernel
+// `kernel` of `src` for the current device; nullptr (error text set) on failure.
+hipFunction_t rtc_function(const std::string &src, const char *kernel);
+
 std::string rtc_generic_source(const RtcSpec &sp, int TX, int TY);
 // Compile the generated kernels of the given tiles (concurrently); false if any failed.
 bool rtc_prepare(const RtcSpec &sp, const std::vector<Tile> &tiles);

@@ -266,3 +266,107 @@ def mlp_init(seed: int = 5, stream: int = 7000):
     w3 = (2 * u[1536 + 4096:] - 1) * np.sqrt(6 / 64)
     z = np.zeros(64)
     return np.concatenate([w1, z, w2, z, w3, [0.0]]).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Pointwise programs (the saturator's input) and their inputs.
+#
+# A program is a dict: n_inputs, n_outputs, n_params, n_locals, radius, insns
+# (postfix instructions (op, a, b, c, d), op codes as in include/saturator.h:
+# 1 CONST, 2 PARAM, 3 LOAD, 4 ADD, 5 SUB, 6 MUL, 7 NEG, 8 STORE, 9 SET,
+# 10 GET) and consts.  Written out by hand here: these are inputs, not
+# arithmetic.
+
+_CONST, _PARAM, _LOAD, _ADD, _SUB, _MUL, _NEG, _STORE, _SET, _GET = range(1, 11)
+
+# Block-tridiagonal assembly of an implicit line solve along z (the shape of
+# the paper's Listing lst:zsolve): for 5 x 5 blocks, with flux Jacobian F and
+# viscous Jacobian N given per point, t1 = dt*tz1 and t2 = dt*tz2,
+#   A[m][n] = -t2*F(k-1) - t1*N(k-1)            (- t1*dz[m]  on the diagonal)
+#   B[m][n] = 2*t1*N(k)                         (+ 1 + 2*t1*dz[m] on the diagonal)
+#   C[m][n] =  t2*F(k+1) - t1*N(k+1)            (- t1*dz[m]  on the diagonal)
+# 75 statements, 125 loads.  Inputs: F[m][n] = array 5m+n, N[m][n] = array
+# 25+5m+n; outputs A, B, C = arrays 5m+n, 25+5m+n, 50+5m+n; params dt, tz1,
+# tz2, dz[0..4]; locals t1, t2.
+LHS_PARAMS = (0.5, 1.0, 4.0, 0.1, 0.2, 0.3, 0.4, 0.5)  # dt, tz1, tz2, dz[0..4]
+LHS_N = (162, 162, 162)
+
+
+def lhs_program():
+    ins = [(_PARAM, 0, 0, 0, 0), (_PARAM, 1, 0, 0, 0), (_MUL, 0, 0, 0, 0), (_SET, 0, 0, 0, 0),
+           (_PARAM, 0, 0, 0, 0), (_PARAM, 2, 0, 0, 0), (_MUL, 0, 0, 0, 0), (_SET, 1, 0, 0, 0)]
+    t1, t2 = (_GET, 0, 0, 0, 0), (_GET, 1, 0, 0, 0)
+    two, one = (_CONST, 0, 0, 0, 0), (_CONST, 1, 0, 0, 0)
+    op = lambda o: (o, 0, 0, 0, 0)  # noqa: E731
+    for m in range(5):  # A
+        for n in range(5):
+            ins += [t2, op(_NEG), (_LOAD, 5 * m + n, 0, 0, -1), op(_MUL),
+                    t1, (_LOAD, 25 + 5 * m + n, 0, 0, -1), op(_MUL), op(_SUB)]
+            if m == n:
+                ins += [t1, (_PARAM, 3 + m, 0, 0, 0), op(_MUL), op(_SUB)]
+            ins.append((_STORE, 5 * m + n, 0, 0, 0))
+    for m in range(5):  # B
+        for n in range(5):
+            ins += [two, t1, op(_MUL), (_LOAD, 25 + 5 * m + n, 0, 0, 0), op(_MUL)]
+            if m == n:
+                ins += [one, two, t1, op(_MUL), (_PARAM, 3 + m, 0, 0, 0), op(_MUL), op(_ADD), op(_ADD)]
+            ins.append((_STORE, 25 + 5 * m + n, 0, 0, 0))
+    for m in range(5):  # C
+        for n in range(5):
+            ins += [t2, (_LOAD, 5 * m + n, 0, 0, 1), op(_MUL), t1, (_LOAD, 25 + 5 * m + n, 0, 0, 1), op(_MUL),
+                    op(_SUB)]
+            if m == n:
+                ins += [t1, (_PARAM, 3 + m, 0, 0, 0), op(_MUL), op(_SUB)]
+            ins.append((_STORE, 50 + 5 * m + n, 0, 0, 0))
+    return dict(n_inputs=50, n_outputs=75, n_params=8, n_locals=2, radius=1, insns=ins, consts=[2.0, 1.0])
+
+
+def lhs_inputs(n=LHS_N, seed: int = 11):
+    """F = 1 + U[0,1) (streams 0..24), N = U[0,1) (streams 25..49) over the
+    padded arrays (halo 1).  With tz2 = 4 tz1 every output is a sum of terms
+    that cannot cancel by more than a factor of about 4."""
+    nx, ny, nz = n
+    shape = (nz + 2, ny + 2, nx + 2)
+    out = []
+    for s in range(50):
+        u = uniform_f64(seed, s, shape)
+        out.append(u + 1.0 if s < 25 else u)
+    return out
+
+
+def random_program(index: int, seed: int = 13, n_inputs: int = 4, n_outputs: int = 3, n_params: int = 3,
+                   max_terms: int = 6, radius: int = 1):
+    """A seeded random program: each output is a sum of products of two or
+    three factors (loads at offsets within `radius`, parameters, constants
+    from {2, 0.5, 3}), some sharing subexpressions with earlier statements;
+    every value positive when inputs and parameters are, so no statement
+    cancels.  Used to exercise the rewriting on shapes beyond the fixed
+    workload."""
+    u = splitmix64(seed, 9000 + index, 0, 4096)
+    it = iter(((u >> np.uint64(11)).astype(np.float64) * 2.0 ** -53).tolist())
+    pick = lambda k: min(k - 1, int(next(it) * k))  # noqa: E731
+    consts = [2.0, 0.5, 3.0]
+    ins = []
+
+    def leaf():
+        c = pick(3)
+        if c == 0:
+            return [(_LOAD, pick(n_inputs), pick(2 * radius + 1) - radius, pick(2 * radius + 1) - radius,
+                     pick(2 * radius + 1) - radius)]
+        if c == 1:
+            return [(_PARAM, pick(n_params), 0, 0, 0)]
+        return [(_CONST, pick(3), 0, 0, 0)]
+
+    shared = leaf() + leaf() + [(_MUL, 0, 0, 0, 0)]
+    for o in range(n_outputs):
+        terms = 1 + pick(max_terms)
+        for t in range(terms):
+            f = (shared if pick(3) == 0 else leaf() + leaf() + [(_MUL, 0, 0, 0, 0)])
+            if pick(2):
+                f = f + leaf() + [(_MUL, 0, 0, 0, 0)]
+            ins += f
+            if t > 0:
+                ins.append((_ADD, 0, 0, 0, 0))
+        ins.append((_STORE, o, 0, 0, 0))
+    return dict(n_inputs=n_inputs, n_outputs=n_outputs, n_params=n_params, n_locals=0, radius=radius, insns=ins,
+                consts=consts)
