@@ -100,14 +100,23 @@ typedef enum { STENCIL_F32 = 1, STENCIL_F64 = 2 } stencil_dtype; /* storage type
  *                 (bit-identical to PLAIN);
  *   ACCSAT_POINT  both (bit-identical to CSE_SAT and to SATURATED, which adds
  *                 the z-streaming register queue and LDS tile).
- * They use the plain launch shapes and are never picked by the tuners. */
+ * They use the plain launch shapes and are never picked by the tuners.
+ *
+ * SATURATED_T2 (POISSON19, Dirichlet): the saturated form with two sweeps per
+ * pass over memory -- the first sweep is recomputed on a one-cell ring around
+ * each tile so the second can follow it plane by plane, and the coefficient
+ * streams are read once per two sweeps.  Bit-identical to SATURATED at the
+ * same tile, z-block and tile map (an odd sweep count starts with one
+ * SATURATED sweep).  Tuned exhaustively (AUTO and the cost model do not
+ * consider it). */
 typedef enum {
     STENCIL_PLAIN = 0,
     STENCIL_SATURATED = 1,
     STENCIL_AUTO = 2,
     STENCIL_CSE_SAT = 3,
     STENCIL_CSE_BULK = 4,
-    STENCIL_ACCSAT_POINT = 5
+    STENCIL_ACCSAT_POINT = 5,
+    STENCIL_SATURATED_T2 = 6
 } stencil_variant;
 /* How a plan picks variant and tile when variant == AUTO or a tile field is 0:
  * FIXED uses library defaults; EXHAUSTIVE times every candidate on the device

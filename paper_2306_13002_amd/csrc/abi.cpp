@@ -86,12 +86,12 @@ Tile default_tile(int kind, int variant, const Geom &g) {
     switch (kind) {
     case STENCIL_HEAT3D7: return Tile{32, 8, g.nz < 8 ? g.nz : 8};
     case STENCIL_POISSON19: return Tile{128, 4, g.nz < 32 ? g.nz : 32};
-    case STENCIL_WAVE25: return Tile{128, 8, g.nz < 128 ? g.nz : 128};
+    case STENCIL_WAVE25: return Tile{64, 32, g.nz < 256 ? g.nz : 256};
     default: return Tile{64, 4, 16};
     }
 }
 
-int default_remap(int kind) { return kind == STENCIL_WAVE25 ? 0 : 1; }
+int default_remap(int) { return 1; }
 
 // GENERIC: build the plain and saturated tap tables and upload them.
 // Plain keeps the caller's order.  Saturated groups taps by (dz, coefficient
@@ -186,10 +186,12 @@ stencil_status validate_desc(const stencil_desc *d, Geom &g, int &rz) {
     const int k = d->kind;
     if (k < STENCIL_HEAT2D5 || k > STENCIL_GENERIC) return fail(STENCIL_E_INVAL, "unknown kind %d", k);
     if (d->dtype != STENCIL_F32 && d->dtype != STENCIL_F64) return fail(STENCIL_E_INVAL, "unknown dtype %d", d->dtype);
-    if (d->variant < STENCIL_PLAIN || d->variant > STENCIL_ACCSAT_POINT)
+    if (d->variant < STENCIL_PLAIN || d->variant > STENCIL_SATURATED_T2)
         return fail(STENCIL_E_INVAL, "unknown variant %d", d->variant);
-    if (d->variant >= STENCIL_CSE_SAT && k != STENCIL_WAVE25 && k != STENCIL_POISSON19)
+    if (is_point_form(d->variant) && k != STENCIL_WAVE25 && k != STENCIL_POISSON19)
         return fail(STENCIL_E_UNSUPPORTED, "the per-point ablation forms are offered for WAVE25 and POISSON19");
+    if (d->variant == STENCIL_SATURATED_T2 && (k != STENCIL_POISSON19 || d->bc != STENCIL_BC_DIRICHLET))
+        return fail(STENCIL_E_UNSUPPORTED, "the two-sweep saturated form is offered for POISSON19 (Dirichlet)");
     if (d->tune < STENCIL_TUNE_FIXED || d->tune > STENCIL_TUNE_MODEL)
         return fail(STENCIL_E_INVAL, "unknown tune mode %d", d->tune);
     if (d->bc != STENCIL_BC_DIRICHLET && d->bc != STENCIL_BC_PERIODIC)
@@ -316,9 +318,10 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     if (d->tile_map < 0 || d->tile_map > 2) return fail(STENCIL_E_INVAL, "tile_map %d not in 0..2", d->tile_map);
     if (d->variant == STENCIL_SATURATED && !has_sat)
         return fail(STENCIL_E_UNSUPPORTED, "kind %d has no saturated form", p->kind);
-    const bool open = d->variant < STENCIL_CSE_SAT &&
+    const bool open = !is_point_form(d->variant) &&
                       (d->variant == STENCIL_AUTO || !d->tile_x || !d->tile_y || !d->zblock || !d->tile_map);
-    if (d->tune == STENCIL_TUNE_MODEL && open) {
+    // the cost model has no timings of the two-sweep form: it is tuned exhaustively
+    if (d->tune == STENCIL_TUNE_MODEL && open && d->variant != STENCIL_SATURATED_T2) {
         TuneRequest rq{has_sat ? d->variant : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map};
         TuneEntry e{};
         stencil_status st = tune_model(p, rq, &e);
@@ -349,7 +352,7 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     }
     int v = d->variant;
     if (v == STENCIL_AUTO) v = has_sat ? V_SATURATED : V_PLAIN;
-    Tile t = default_tile(p->kind, v >= V_CSE_SAT ? V_PLAIN : v, p->g);
+    Tile t = default_tile(p->kind, is_point_form(v) ? V_PLAIN : (v == V_SAT2 ? V_SATURATED : v), p->g);
     if (d->tile_x) t.tx = d->tile_x;
     if (d->tile_y) t.ty = d->tile_y;
     if (d->zblock) t.tz = d->zblock;
@@ -460,13 +463,22 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
     // Jacobi kinds read fields[0] first; the leapfrog reads the newer level
     // fields[1] and overwrites the older fields[0] in place.
     void *src = wave ? fields[1] : fields[0], *dst = wave ? fields[0] : fields[1];
-    for (int t = 0; t < iterations; ++t) {
+    // A launch of the two-sweep form advances two sweeps; an odd count starts
+    // with one single saturated sweep at the same shape, so the last launch
+    // (the one that leaves the residual partials) is always of the plan's form.
+    const int per = sweeps_per_launch(p->variant);
+    int launches = 0;
+    for (int t = 0; t < iterations;) {
         if (p->bc == STENCIL_BC_PERIODIC && (e = launch_periodic_fill(src, eb, p->g, p->rz, s)) != hipSuccess)
             return hip_fail(e, "periodic fill launch");
+        const int v = (t == 0 && (iterations % per)) ? V_SATURATED : p->variant;
+        const int adv = sweeps_per_launch(v);
         a.src = src;
         a.dst = dst;
-        a.part = (t == iterations - 1) ? p->d_part : nullptr;
-        if ((e = p->ops->launch(p->variant, p->tile, a, s)) != hipSuccess) return hip_fail(e, "sweep launch");
+        a.part = (t + adv == iterations) ? p->d_part : nullptr;
+        if ((e = p->ops->launch(v, p->tile, a, s)) != hipSuccess) return hip_fail(e, "sweep launch");
+        t += adv;
+        ++launches;
         void *tmp = src;
         src = dst;
         dst = tmp;
@@ -476,7 +488,7 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
         p->prof_sweeps = iterations;
         p->prof_valid = true;
     }
-    if (!wave && (iterations & 1)) {
+    if (!wave && (launches & 1)) {
         if ((e = launch_interior_copy(fields[1], fields[0], eb, p->g, p->rz, s)) != hipSuccess)
             return hip_fail(e, "tail copy launch");
     }

@@ -168,6 +168,6 @@ hipError_t gen_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 
 }  // namespace
 
-KindOps generic_ops = {gen_tile_ok, gen_sat_tiles, gen_nblocks, gen_launch, nullptr};
+KindOps generic_ops = {gen_tile_ok, gen_sat_tiles, nullptr, gen_nblocks, gen_launch, nullptr};
 
 }  // namespace stn

@@ -270,7 +270,7 @@ hipError_t h3_batch_launch(int v, Tile t, const BatchProb *probs, const BatchIte
 
 }  // namespace
 
-KindOps heat2d5_ops = {h2_tile_ok, nullptr, h2_nblocks, h2_launch, nullptr};
-KindOps heat3d7_ops = {h3_tile_ok, h3_sat_tiles, h3_nblocks, h3_launch, h3_batch_launch};
+KindOps heat2d5_ops = {h2_tile_ok, nullptr, nullptr, h2_nblocks, h2_launch, nullptr};
+KindOps heat3d7_ops = {h3_tile_ok, h3_sat_tiles, nullptr, h3_nblocks, h3_launch, h3_batch_launch};
 
 }  // namespace stn

@@ -8,8 +8,12 @@
 namespace stn {
 
 // Forms.  V_CSE_SAT, V_CSE_BULK and V_ACCSAT_POINT are the per-point forms of
-// the paper's ablation (rewritten arithmetic only, bulk load only, both).
-enum Variant { V_PLAIN = 0, V_SATURATED = 1, V_CSE_SAT = 3, V_CSE_BULK = 4, V_ACCSAT_POINT = 5 };
+// the paper's ablation (rewritten arithmetic only, bulk load only, both);
+// V_SAT2 is the saturated form with two sweeps per pass (POISSON19).
+enum Variant { V_PLAIN = 0, V_SATURATED = 1, V_CSE_SAT = 3, V_CSE_BULK = 4, V_ACCSAT_POINT = 5, V_SAT2 = 6 };
+inline bool is_point_form(int v) { return v == V_CSE_SAT || v == V_CSE_BULK || v == V_ACCSAT_POINT; }
+// Sweeps one launch performs.
+inline int sweeps_per_launch(int v) { return v == V_SAT2 ? 2 : 1; }
 
 // Launch shape.  Plain forms: block = (tx, ty, tz) threads, one per point.
 // Saturated forms: tx threads along x, a tile of ty rows, zblock planes
@@ -64,6 +68,7 @@ struct BatchItem {
 struct KindOps {
     bool (*tile_ok)(int variant, Tile t);
     int (*sat_tiles)(Tile *out, int max);  // offered saturated (tx, ty) shapes; nullptr if none
+    int (*sat2_tiles)(Tile *out, int max);  // shapes of the two-sweep saturated form; nullptr if none
     long long (*nblocks)(int variant, Tile t, const Geom &g);
     hipError_t (*launch)(int variant, Tile t, const SweepArgs &a, hipStream_t s);
     // Persistent work-list sweep over a batch (nullptr: kind not batchable).

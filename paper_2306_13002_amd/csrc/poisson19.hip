@@ -259,17 +259,201 @@ __global__ __launch_bounds__(TX *TY) void poisson19_sat(const float *__restrict_
     }
 }
 
+// The saturated update of one point from three staged planes (m, o, u =
+// planes zc-1, zc, zc+1 of an LDS tile of row width W) and the point's 12
+// coefficients; returns ss and the new value rounded to F32.  The same
+// operations in the same order as poisson19_sat.
+template <int W>
+__device__ __forceinline__ double p19_update(const float *m, const float *o, const float *u, int e, const float *cc,
+                                             double omega, float *out) {
+    const double pc = o[e];
+    const double pE = o[e + 1], pW = o[e - 1], pN = o[e + W], pS = o[e - W];
+    const double B0v = ((double)o[e + W + 1] - (double)o[e - W + 1]) - ((double)o[e + W - 1] - (double)o[e - W - 1]);
+    const double B1v = ((double)u[e + W] - (double)u[e - W]) - ((double)m[e + W] - (double)m[e - W]);
+    const double B2v = ((double)u[e + 1] - (double)u[e - 1]) - ((double)m[e + 1] - (double)m[e - 1]);
+    const double pU = u[e], pD = m[e];
+    double s0 = fma((double)cc[B0], B0v, (double)cc[WRK1]);
+    s0 = fma((double)cc[B1], B1v, s0);
+    s0 = fma((double)cc[B2], B2v, s0);
+    s0 = fma((double)cc[A0], pE, s0);
+    s0 = fma((double)cc[C0], pW, s0);
+    s0 = fma((double)cc[A1], pN, s0);
+    s0 = fma((double)cc[C1], pS, s0);
+    s0 = fma((double)cc[A2], pU, s0);
+    s0 = fma((double)cc[C2], pD, s0);
+    const double ss = fma(s0, (double)cc[A3], -pc) * (double)cc[BND];
+    *out = (float)fma(omega, ss, pc);
+    return ss;
+}
+
+// SATURATED, two sweeps per pass over memory (temporal blocking).  A block
+// owns a TX x TY output tile and streams z.  Sweep 1 is computed on the tile
+// plus a one-cell ring (its values are needed by sweep 2's neighbours and are
+// recomputed by every block that needs them, never exchanged), from an LDS
+// ring of p^t planes with a two-cell halo; sweep 2 is computed on the tile
+// from an LDS ring of the sweep-1 planes and written out.  The 12 coefficient
+// streams and p are read once per two sweeps: 56 algorithmic bytes per two
+// point updates.  Every value is the one two launches of poisson19_sat would
+// produce (same operations, sweep-1 values rounded to F32 as if stored), so
+// the result and the residual (sum of ss^2 of the second sweep) match it bit
+// for bit.  Cells of the ring that are boundary cells keep their fixed value.
+template <int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void poisson19_sat2(const float *__restrict__ p, float *__restrict__ pn,
+                                                         P19Coef c, Geom g, double omega, int zb, int remap,
+                                                         double *__restrict__ part) {
+    constexpr int W0 = TX + 4, PL0 = (TY + 4) * W0;  // p^t tile, two-cell halo
+    constexpr int W1 = TX + 2, PL1 = (TY + 2) * W1;  // sweep-1 tile, one-cell ring
+    constexpr int NT = TX * TY, RS = 2 * W1 + 2 * TY;
+    static_assert(RS <= NT, "every ring cell needs a thread");
+    __shared__ float r0[4][PL0];
+    __shared__ float r1[4][PL1];
+    __shared__ double red[kMaxWaves];
+    int bx, by, bz;
+    tile_coords(remap, bx, by, bz);
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+    const int PX = g.nx + 2, PY = g.ny + 2;
+    const int k0 = bz * zb, k1 = min(k0 + zb, g.nz);  // output planes zc = k0+1 .. k1 (padded)
+
+    // own cell: sweep-1 cell (tx+1, ty+1) of the ring tile, output cell of sweep 2
+    const int xo = bx * TX + tx + 1, yo = by * TY + ty + 1;  // padded coordinates
+    const bool in_o = xo <= g.nx && yo <= g.ny;
+    const bool ld_o = xo < PX && yo < PY;
+    const long long col_o = (long long)yo * g.py + xo;
+    const int e0_o = (ty + 2) * W0 + tx + 2, e1_o = (ty + 1) * W1 + tx + 1;
+    // ring cell of the sweep-1 tile handled by this thread (tid < RS)
+    int ex = 0, ey = 0;
+    if (tid < W1) {
+        ex = tid;
+    } else if (tid < 2 * W1) {
+        ex = tid - W1;
+        ey = TY + 1;
+    } else if (tid < 2 * W1 + TY) {
+        ey = tid - 2 * W1 + 1;
+    } else {
+        ex = W1 - 1;
+        ey = tid - 2 * W1 - TY + 1;
+    }
+    const bool has_r = tid < RS;
+    const int xr = bx * TX + ex, yr = by * TY + ey;  // padded
+    const bool in_r = has_r && xr >= 1 && xr <= g.nx && yr >= 1 && yr <= g.ny;
+    const long long col_r = (long long)yr * g.py + xr;
+    const int e0_r = (ey + 1) * W0 + ex + 1, e1_r = ey * W1 + ex;
+
+    HaloStager<float, TX, TY, 2, true, NT> halo;
+    halo.init(tid, bx * TX + 1, by * TY + 1, g.py, PX, PY);
+
+    const int zlo = k0, zhi = k1 + 1;  // sweep-1 planes computed: zlo .. zhi (padded)
+    // prologue: p^t planes zlo-1 (if any) and zlo into LDS, zlo+1 into registers
+    for (int z = zlo - 1; z <= zlo; ++z) {
+        if (z < 0) continue;
+        const float *pl = p + (long long)z * g.pz;
+        r0[z & 3][e0_o] = ld_o ? pl[col_o] : 0.0f;
+        halo.load(pl);
+        halo.store(r0[z & 3]);
+    }
+    float ctr = ld_o ? p[col_o + (long long)(zlo + 1) * g.pz] : 0.0f;
+    halo.load(p + (long long)(zlo + 1) * g.pz);
+    // coefficients of the sweep-1 plane about to be computed (own and ring
+    // cell), and of the own cell for the two planes before it (sweep 2 runs
+    // two planes behind sweep 1)
+    float cf_o[12], cf_r[12], c1_o[12], c2_o[12];
+    {
+        const bool zin = zlo >= 1 && zlo <= g.nz;
+        const long long qo = col_o + (long long)zlo * g.pz, qr = col_r + (long long)zlo * g.pz;
+#pragma unroll
+        for (int s = 0; s < 12; ++s) {
+            cf_o[s] = (zin && in_o) ? c.f[s][qo] : 0.0f;
+            cf_r[s] = (zin && in_r) ? c.f[s][qr] : 0.0f;
+            c1_o[s] = 0.0f;
+            c2_o[s] = 0.0f;
+        }
+    }
+    double acc = 0.0;
+
+    // Iteration zA: sweep 1 at plane zA, sweep 2 at plane zA-2 (its inputs,
+    // sweep-1 planes zA-3 .. zA-1, were written in earlier iterations), so one
+    // barrier per plane separates every LDS write from its readers.
+    for (int zA = zlo; zA <= zhi + 1; ++zA) {
+        float cc_o[12], cc_r[12];
+#pragma unroll
+        for (int s = 0; s < 12; ++s) {
+            cc_o[s] = cf_o[s];
+            cc_r[s] = cf_r[s];
+        }
+        if (zA <= zhi) {
+            // stage p^t plane zA+1, then issue every load of the next plane
+            r0[(zA + 1) & 3][e0_o] = ctr;
+            halo.store(r0[(zA + 1) & 3]);
+            if (zA < zhi) {
+                if (zA + 2 <= g.nz + 1) {
+                    const float *pl = p + (long long)(zA + 2) * g.pz;
+                    ctr = ld_o ? pl[col_o] : 0.0f;
+                    halo.load(pl);
+                }
+                const bool zin = zA + 1 >= 1 && zA + 1 <= g.nz;
+                const long long qo = col_o + (long long)(zA + 1) * g.pz, qr = col_r + (long long)(zA + 1) * g.pz;
+#pragma unroll
+                for (int s = 0; s < 12; ++s) {
+                    cf_o[s] = (zin && in_o) ? c.f[s][qo] : 0.0f;
+                    cf_r[s] = (zin && in_r) ? c.f[s][qr] : 0.0f;
+                }
+            }
+        }
+        __syncthreads();
+        if (zA <= zhi) {  // sweep 1 at plane zA on the tile and its ring
+            const bool zin = zA >= 1 && zA <= g.nz;
+            const float *m = r0[(zA - 1) & 3], *o = r0[zA & 3], *u = r0[(zA + 1) & 3];
+            float v;
+            if (zin && in_o) p19_update<W0>(m, o, u, e0_o, cc_o, omega, &v);
+            else v = o[e0_o];
+            r1[zA & 3][e1_o] = v;
+            if (has_r) {
+                if (zin && in_r) p19_update<W0>(m, o, u, e0_r, cc_r, omega, &v);
+                else v = o[e0_r];
+                r1[zA & 3][e1_r] = v;
+            }
+        }
+        const int zc = zA - 2;  // sweep 2 at plane zc, from sweep-1 planes zc-1 .. zc+1
+        if (zc >= k0 + 1 && in_o) {
+            const float *m = r1[(zc - 1) & 3], *o = r1[zc & 3], *u = r1[(zc + 1) & 3];
+            float v;
+            const double ss = p19_update<W1>(m, o, u, e1_o, c2_o, omega, &v);
+            pn[col_o + (long long)zc * g.pz] = v;
+            acc = fma(ss, ss, acc);
+        }
+#pragma unroll
+        for (int s = 0; s < 12; ++s) {
+            c2_o[s] = c1_o[s];
+            c1_o[s] = cc_o[s];
+        }
+    }
+    if (part) {
+        const double s = block_sum_f64(acc, red);
+        if (tid == 0) part[block_linear_id()] = s;
+    }
+}
+
 bool plain_tile_ok(Tile t) {
     const long long n = (long long)t.tx * t.ty * t.tz;
     return t.tx >= 1 && t.ty >= 1 && t.tz >= 1 && n % 64 == 0 && n <= 1024;
 }
 
 #define P19_SAT_TILES(X) X(32, 2) X(32, 4) X(32, 8) X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(128, 1) X(128, 2) \
-    X(128, 4) X(256, 1)
+    X(128, 4) X(128, 8) X(256, 1) X(256, 4)
+// Two-sweep tiles: every cell of the one-cell ring around the tile needs a
+// thread (2(TX+2) + 2 TY <= TX TY); each is also a single-sweep tile (an odd
+// sweep count starts with one single sweep at the same shape).
+#define P19_SAT2_TILES(X) X(32, 4) X(32, 8) X(64, 4) X(64, 8) X(128, 4) X(128, 8) X(256, 4)
 
 bool p19_tile_ok(int v, Tile t) {
-    if (v == V_PLAIN || v >= V_CSE_SAT) return plain_tile_ok(t);
+    if (v == V_PLAIN || is_point_form(v)) return plain_tile_ok(t);
     if (t.tz < 1) return false;
+    if (v == V_SAT2) {
+#define X(a, b) if (t.tx == a && t.ty == b) return true;
+        P19_SAT2_TILES(X)
+#undef X
+        return false;
+    }
 #define X(a, b) if (t.tx == a && t.ty == b) return true;
     P19_SAT_TILES(X)
 #undef X
@@ -280,6 +464,14 @@ int p19_sat_tiles(Tile *out, int max) {
     int n = 0;
 #define X(a, b) if (n < max) out[n++] = Tile{a, b, 0};
     P19_SAT_TILES(X)
+#undef X
+    return n;
+}
+
+int p19_sat2_tiles(Tile *out, int max) {
+    int n = 0;
+#define X(a, b) if (n < max) out[n++] = Tile{a, b, 0};
+    P19_SAT2_TILES(X)
 #undef X
     return n;
 }
@@ -295,12 +487,23 @@ hipError_t p19_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(poisson19_plain, grid, dim3(t.tx, t.ty, t.tz), 0, s, src, dst, c, a.g, a.omega, a.part);
         return hipGetLastError();
     }
-    if (v >= V_CSE_SAT) {
+    if (is_point_form(v)) {
         const dim3 blk(t.tx, t.ty, t.tz);
         if (v == V_CSE_SAT) hipLaunchKernelGGL(poisson19_point<FORM_SAT>, grid, blk, 0, s, src, dst, c, a.g, a.omega, a.part);
         else if (v == V_CSE_BULK) hipLaunchKernelGGL(poisson19_point<FORM_BULK>, grid, blk, 0, s, src, dst, c, a.g, a.omega, a.part);
         else hipLaunchKernelGGL(poisson19_point<FORM_BOTH>, grid, blk, 0, s, src, dst, c, a.g, a.omega, a.part);
         return hipGetLastError();
+    }
+    if (v == V_SAT2) {
+#define X(A, B)                                                                                           \
+    if (t.tx == A && t.ty == B) {                                                                         \
+        hipLaunchKernelGGL((poisson19_sat2<A, B>), grid, dim3(A, B, 1), 0, s, src, dst, c, a.g, a.omega, t.tz, \
+                           a.remap, a.part);                                                              \
+        return hipGetLastError();                                                                         \
+    }
+        P19_SAT2_TILES(X)
+#undef X
+        return hipErrorInvalidValue;
     }
 #define X(A, B)                                                                                          \
     if (t.tx == A && t.ty == B) {                                                                        \
@@ -315,6 +518,6 @@ hipError_t p19_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 
 }  // namespace
 
-KindOps poisson19_ops = {p19_tile_ok, p19_sat_tiles, p19_nblocks, p19_launch, nullptr};
+KindOps poisson19_ops = {p19_tile_ok, p19_sat_tiles, p19_sat2_tiles, p19_nblocks, p19_launch, nullptr};
 
 }  // namespace stn

@@ -87,6 +87,21 @@ std::vector<Cand> tune_candidates(const KindOps *ops, int kind, const Geom &g, c
     if (want_v(V_PLAIN))
         for (const Tile &t : kPlainTiles)
             if (ops->tile_ok(V_PLAIN, t) && tile_fits(t)) out.push_back({V_PLAIN, t, 0});
+    if (rq.variant == V_SAT2 && ops->sat2_tiles) {  // only when asked for: see STENCIL_SATURATED_T2
+        Tile st[64];
+        const int ns = ops->sat2_tiles(st, 64);
+        std::vector<int> zbs;
+        for (int zb : kZblocks)
+            if (zb < g.nz) zbs.push_back(zb);
+        zbs.push_back(g.nz);
+        for (int s = 0; s < ns; ++s)
+            for (int zb : zbs) {
+                Tile t{st[s].tx, st[s].ty, zb};
+                if (!ops->tile_ok(V_SAT2, t) || !tile_fits(t)) continue;
+                for (int m = 1; m <= 2; ++m)
+                    if (!rq.tile_map || rq.tile_map == m) out.push_back({V_SAT2, t, m == 2 ? 1 : 0});
+            }
+    }
     if (want_v(V_SATURATED) && ops->sat_tiles) {
         Tile st[64];
         const int ns = ops->sat_tiles(st, 64);
@@ -174,7 +189,7 @@ static double time_one(const stencil_plan_s *p, const Cand &c, Buffers &b, hipSt
         if ((*err = hipEventSynchronize(e1)) != hipSuccess) return 0;
         float ms = 0;
         if ((*err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return 0;
-        if (r > 0) ts.push_back(1e3 * ms / T);
+        if (r > 0) ts.push_back(1e3 * ms / (T * sweeps_per_launch(c.variant)));
     }
     std::sort(ts.begin(), ts.end());
     return ts[ts.size() / 2];

@@ -21,8 +21,11 @@ pytestmark = pytest.mark.gpu
 PLAIN_TILES = [(64, 4, 1), (64, 2, 2), (128, 2, 1), (256, 1, 1), (32, 8, 1), (64, 8, 1)]
 HEAT_SAT_TILES = [(32, 2), (32, 4), (32, 8), (64, 1), (64, 2), (64, 4), (64, 8), (128, 1), (128, 2), (128, 4),
                   (256, 1), (256, 2)]
-P19_SAT_TILES = [(32, 2), (32, 4), (32, 8), (64, 1), (64, 2), (64, 4), (64, 8), (128, 1), (128, 2), (128, 4), (256, 1)]
-W25_SAT_TILES = [(64, 4), (64, 8), (64, 16), (32, 8), (32, 16), (128, 4), (128, 8), (256, 4)]
+P19_SAT_TILES = [(32, 2), (32, 4), (32, 8), (64, 1), (64, 2), (64, 4), (64, 8), (128, 1), (128, 2), (128, 4), (128, 8),
+                 (256, 1), (256, 4)]
+P19_SAT2_TILES = [(32, 4), (32, 8), (64, 4), (64, 8), (128, 4), (128, 8), (256, 4)]
+W25_SAT_TILES = [(64, 4), (64, 8), (64, 16), (64, 32), (32, 8), (32, 16), (128, 4), (128, 8), (128, 16), (256, 4),
+                 (256, 8)]
 
 
 @pytest.fixture(scope="module")
@@ -157,7 +160,37 @@ def test_poisson19_saturated(dev, tile, zb):
     assert np.array_equal(got[0], p0[0]) and np.array_equal(got[:, 0], p0[:, 0])
 
 
-@pytest.mark.parametrize("variant", ["plain", "saturated"])
+@pytest.mark.parametrize("tile", P19_SAT2_TILES)
+@pytest.mark.parametrize("zb", [1, 5, 64])
+@pytest.mark.parametrize("remap", ["natural", "xcd"])
+def test_poisson19_two_sweep_equals_saturated_bitwise(dev, tile, zb, remap):
+    """Two sweeps per pass give exactly what the single-sweep saturated
+    kernel gives, for even and odd sweep counts, residual included."""
+    p0, cf = _p19_inputs(seed=4)
+    for T in (1, 2, 3, 4, 5):
+        ref, gr = run_jacobi("poisson19", p0, NP, dev, T, coefs=cf, variant="saturated",
+                             tile=(tile[0], tile[1], zb), omega=0.8, tile_map=remap)
+        got, gg = run_jacobi("poisson19", p0, NP, dev, T, coefs=cf, variant="saturated_t2",
+                             tile=(tile[0], tile[1], zb), omega=0.8, tile_map=remap)
+        assert np.array_equal(got, ref), T
+        assert gg == gr, T
+
+
+@pytest.mark.parametrize("tile", [(128, 4), (64, 8), (256, 4)])
+def test_poisson19_two_sweep_vs_oracle(dev, tile):
+    p0, cf = _p19_inputs(seed=6)
+    T = 4
+    w64, _ = oracle.poisson19(p0, cf, 0.8, T, mode="F64")
+    w32, g32 = oracle.poisson19(p0, cf, 0.8, T, mode="F32STORE")
+    got, gg = run_jacobi("poisson19", p0, NP, dev, T, coefs=cf, variant="saturated_t2", tile=(tile[0], tile[1], 8),
+                         omega=0.8)
+    assert maxrel(inner(got, 1), inner(w64, 1)) <= 1e-5
+    assert np.mean(inner(got, 1).astype(np.float64) != inner(w32, 1)) < 1e-3
+    assert abs(gg - g32) <= 1e-5 * g32
+    assert np.array_equal(got[0], p0[0]) and np.array_equal(got[:, 0], p0[:, 0])
+
+
+@pytest.mark.parametrize("variant", ["plain", "saturated", "saturated_t2"])
 def test_poisson19_workload_full(dev, variant):
     # the 129 x 129 x 257 (boundary included) workload, T = 20, as benchmarked
     p0, cf = synth.poisson19_inputs()

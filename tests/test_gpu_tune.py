@@ -91,3 +91,26 @@ def test_tune_cache_file_roundtrip(tmp_path):
     cfg2 = [l for l in r2.stdout.splitlines() if l.startswith("CFG")]
     assert cfg1 == cfg2
     assert len(cache.read_text().strip().splitlines()) == 1
+
+
+def test_tuned_two_sweep_poisson19(dev):
+    """The two-sweep form is tuned only when asked for; its pick is one of its
+    own shapes and its result equals the single-sweep form at that shape."""
+    from paper_2306_13002_amd.stencil import Plan
+    n = (50, 21, 30)
+    p0, cf = synth.poisson19_random_inputs((n[2] + 2, n[1] + 2, n[0] + 2), seed=9)
+    p = Plan("poisson19", n, variant="saturated_t2", omega=0.8, tune="exhaustive")
+    cfg = p.config()
+    assert cfg["variant"] == "saturated_t2"
+    assert tuple(cfg["tile"][:2]) in [(32, 4), (32, 8), (64, 4), (64, 8), (128, 4), (128, 8), (256, 4)]
+    outs = []
+    for plan in (p, Plan("poisson19", n, variant="saturated", omega=0.8, tile=cfg["tile"], tile_map=cfg["tile_map"])):
+        f = [torch.tensor(p0, device=dev), torch.full(p0.shape, float("nan"), dtype=torch.float32, device=dev)]
+        plan.run(f, [torch.tensor(c, device=dev) for c in cf], iterations=6)
+        outs.append((f[0].cpu().numpy(), plan.residual()))
+        plan.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    # AUTO never offers it
+    a = Plan("poisson19", n, variant="auto", omega=0.8, tune="exhaustive")
+    assert a.config()["variant"] in ("plain", "saturated")
+    a.close()
