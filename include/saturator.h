@@ -113,7 +113,7 @@ typedef struct {
 } sat_stats;
 
 /* Rewrite and generate (host only, no GPU needed).  Writes the generated HIP
- * source (kernel "sat_kernel") to src[0..src_len) and the extracted program
+ * source (kernel "sat_kernel_<form>", e.g. sat_kernel_accsat) to src[0..src_len) and the extracted program
  * as single-assignment text to ssa[0..ssa_len), both NUL-terminated; either
  * buffer may be NULL.  SSA lines:  "v<N> = <op> <args>"  with op one of
  * const <hexfloat> | param <p> | load <a> <dx> <dy> <dz> | add | sub | mul |

@@ -127,7 +127,7 @@ stencil_status sat_plan(const sat_program_desc *d, int32_t form, int32_t tile_x,
     if (!err.empty()) return fail(STENCIL_E_INVAL, "%s", err.c_str());
     logf("saturator form %d: %d e-nodes, %d e-classes, %d iterations, cost %.0f -> %.0f, %d loads %d ops", form,
          g.st.enodes, g.st.eclasses, g.st.iterations, g.st.cost_input, g.st.cost_extracted, g.st.loads, g.st.ops);
-    hipFunction_t fn = rtc_function(g.src, "sat_kernel");
+    hipFunction_t fn = rtc_function(g.src, sat::kernel_name(form));
     if (!fn) return STENCIL_E_DEVICE;  // error text set by rtc_function
     sat_plan_s *pl = new (std::nothrow) sat_plan_s;
     if (!pl) return fail(STENCIL_E_NOMEM, "plan allocation");

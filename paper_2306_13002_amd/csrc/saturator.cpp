@@ -833,6 +833,16 @@ const char *kFormName[] = {"PLAIN", "CSE", "CSE+SAT", "CSE+BULK", "ACCSAT"};
 
 }  // namespace
 
+const char *kernel_name(int form) {
+    static const char *names[] = {"sat_kernel_plain", "sat_kernel_cse", "sat_kernel_cse_sat", "sat_kernel_cse_bulk",
+                                  "sat_kernel_accsat"};
+    return names[form];
+}
+
+namespace {
+
+}  // namespace
+
 std::string validate(Program &p) {
     char b[256];
     if (p.n_in < 0 || p.n_in > 128) return "n_inputs must be in [0, 128]";
@@ -1006,13 +1016,13 @@ std::string generate(const Program &p, int form, int extract, int tx, int ty, co
                   NI, p.n_out, NP);
     s += b;
     std::snprintf(b, sizeof b,
-                  "extern \"C\" __global__ __launch_bounds__(%d) void sat_kernel(SatArgs A) {\n"
+                  "extern \"C\" __global__ __launch_bounds__(%d) void %s(SatArgs A) {\n"
                   "    const int i = (int)(blockIdx.x * %d + threadIdx.x);\n"
                   "    const int j = (int)(blockIdx.y * %d + threadIdx.y);\n"
                   "    const int k = (int)blockIdx.z;\n"
                   "    if (i >= %lld || j >= %lld) return;\n"
                   "    const long long o = (long long)(k + %d) * %lldLL + (long long)(j + %d) * %lldLL + (i + %d);\n",
-                  tx * ty, tx, ty, p.n[0], p.n[1], p.radius, p.pz, p.radius, p.py, p.radius);
+                  tx * ty, kernel_name(form), tx, ty, p.n[0], p.n[1], p.radius, p.pz, p.radius, p.py, p.radius);
     s += b;
     s += E.body;
     s += "}\n";

@@ -56,6 +56,9 @@ struct Limits {
     double max_extract_s = 30.0;
 };
 
+// Name of the generated kernel of a form ("sat_kernel_<form>").
+const char *kernel_name(int form);
+
 // Check a program; returns "" or the reason it is rejected.
 std::string validate(Program &p);
 

@@ -244,15 +244,21 @@ __global__ __launch_bounds__(TX *BY) void wave25_sat(const double *__restrict__ 
             }
         }
         __syncthreads();
+        // y neighbours that are rows of this same thread come from its own
+        // registers (the value in the LDS tile is the same number)
+        auto yv = [&](int m, int d) -> double {
+            const int mm = m + d;
+            return (mm >= 0 && mm < RY) ? q[mm >= 0 && mm < RY ? mm : 0][4] : t[me[m] + d * W];
+        };
 #pragma unroll
         for (int m = 0; m < RY; ++m) {
             if (in[m]) {
                 const int e = me[m];
                 const double u = q[m][4];
-                const double s1 = ((t[e - 1] + t[e + 1]) + (t[e - W] + t[e + W])) + (q[m][3] + q[m][5]);
-                const double s2 = ((t[e - 2] + t[e + 2]) + (t[e - 2 * W] + t[e + 2 * W])) + (q[m][2] + q[m][6]);
-                const double s3 = ((t[e - 3] + t[e + 3]) + (t[e - 3 * W] + t[e + 3 * W])) + (q[m][1] + q[m][7]);
-                const double s4 = ((t[e - 4] + t[e + 4]) + (t[e - 4 * W] + t[e + 4 * W])) + (q[m][0] + q[m][8]);
+                const double s1 = ((t[e - 1] + t[e + 1]) + (yv(m, -1) + yv(m, 1))) + (q[m][3] + q[m][5]);
+                const double s2 = ((t[e - 2] + t[e + 2]) + (yv(m, -2) + yv(m, 2))) + (q[m][2] + q[m][6]);
+                const double s3 = ((t[e - 3] + t[e + 3]) + (yv(m, -3) + yv(m, 3))) + (q[m][1] + q[m][7]);
+                const double s4 = ((t[e - 4] + t[e + 4]) + (yv(m, -4) + yv(m, 4))) + (q[m][0] + q[m][8]);
                 double L = c.c0x3 * u;
                 L = fma(c.c1, s1, L);
                 L = fma(c.c2, s2, L);

@@ -262,7 +262,7 @@ def test_bulk_forms_issue_every_load_first_in_address_order():
 
 def test_generated_source_shape():
     src, _, st = X.generate(synth.lhs_program(), (162, 162, 162), "accsat", tile=(64, 4))
-    assert 'extern "C" __global__ __launch_bounds__(256) void sat_kernel(SatArgs A)' in src
+    assert 'extern "C" __global__ __launch_bounds__(256) void sat_kernel_accsat(SatArgs A)' in src
     assert src.count("A.in[") == 125 and src.count("A.out[") == 75
     assert "fma(" in src and "__restrict__" not in src  # the program's arrays may alias, as written
 
