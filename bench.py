@@ -223,17 +223,21 @@ def time_variant(name, variant, steps, warmup, dev, torch, synth, Plan, plan_kw=
     # same work on the same grid (the restore copy is done once, untimed).
     reset()
     torch.cuda.synchronize()
+    per_step = []
     t0 = time.perf_counter()
     for _ in range(steps):
         resid = step()
         ms, n = plan.profile_read()
         sweep_ms += ms
         sweeps += n
+        per_step.append(ms / max(1, n))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     cfg = plan.config()
     plan.close()
-    return dict(wall=wall, pts=pts, sweep_ms=sweep_ms, sweeps=sweeps, resid=resid, meta=meta, cfg=cfg, T=T)
+    per_step.sort()
+    return dict(wall=wall, pts=pts, sweep_ms=sweep_ms, sweeps=sweeps, resid=resid, meta=meta, cfg=cfg, T=T,
+                sweep_ms_median=per_step[len(per_step) // 2], sweep_ms_best=per_step[0])
 
 
 def cpu_baseline(name):
@@ -245,10 +249,11 @@ def cpu_baseline(name):
 
     if name == "poisson19":
         p0, cf = synth.poisson19_inputs()
+        oracle.poisson19(p0, cf, 0.8, 1, mode="F32STORE")  # warm the oracle library and caches
         t = time.perf_counter()
-        oracle.poisson19(p0, cf, 0.8, 2, mode="F32STORE")
-        one = (time.perf_counter() - t) / 2
-        k = max(2, min(4000, int(25.0 / max(one, 1e-3))))
+        oracle.poisson19(p0, cf, 0.8, 8, mode="F32STORE")
+        one = (time.perf_counter() - t) / 8
+        k = max(2, min(4000, int(20.0 / max(one, 1e-3))))
         t = time.perf_counter()
         oracle.poisson19(p0, cf, 0.8, k, mode="F32STORE")
         dt = time.perf_counter() - t
@@ -447,6 +452,9 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_us": launch_s * 1e6,
+            "median_launch_us": main_r["sweep_ms_median"] * 1e3 * per_launch,
+            "best_launch_us": main_r["sweep_ms_best"] * 1e3 * per_launch,
+            "traffic_gbs": traffic / launch_s / 1e9 if traffic else None,
         },
         "residual": main_r["resid"],
     }

@@ -392,3 +392,50 @@ def test_bad_shapes_rejected():
         X.generate(prog, (8, 0, 8), "cse")
     with pytest.raises(S.StencilError, match="pitch_y"):
         X.generate(prog, (8, 8, 8), "cse", pitch=(9, 0))
+
+
+def _stencil_program(taps, cids, coef, grouped):
+    """One output: the generic stencil sum_t coef[cid_t] * u(x + delta_t),
+    written tap by tap (plain) or as the hand-grouped saturated form (taps
+    sharing a coefficient and a z offset summed, then one product per group)."""
+    p = X.Program(n_inputs=1, n_outputs=1, radius=max(max(abs(v) for v in t) for t in taps))
+    u = X.In(0)
+    if not grouped:
+        e = None
+        for t, c in zip(taps, cids):
+            term = X.Const(coef[c]) * u.at(*t)
+            e = term if e is None else e + term
+    else:
+        groups = {}
+        for t, c in zip(taps, cids):
+            groups.setdefault((t[2], c), []).append(tuple(t))
+        e = None
+        for (dz, c), ts in sorted(groups.items()):
+            s = None
+            for t in sorted(ts, key=lambda q: (q[1], q[0])):
+                s = u.at(*t) if s is None else s + u.at(*t)
+            term = X.Const(coef[c]) * s
+            e = term if e is None else e + term
+    p.store(0, e)
+    return p
+
+
+@pytest.mark.parametrize("idx", [2, 3, 4, 5, 7])
+def test_engine_on_generic_stencils_matches_or_beats_the_hand_grouping(idx):
+    """The generic stencils' saturated kernels use a hand rule (group sums,
+    one product per group).  Under the paper's cost model the e-graph,
+    started from the plain tap-by-tap sum, finds a form at least as cheap
+    (FMA chains tie with factoring: both need one operation per tap), and
+    every form is the same polynomial."""
+    s = synth.generic_stencil(idx, max_edge=16)
+    taps, cids, coef = [tuple(t) for t in s["taps"]], list(s["cids"]), list(s["coef"])
+    plain = _stencil_program(taps, cids, coef, grouped=False)
+    grouped = _stencil_program(taps, cids, coef, grouped=True)
+    _, ssa_e, st_e = X.generate(plain, (8, 8, 8), "cse_sat")
+    _, ssa_g, st_g = X.generate(grouped, (8, 8, 8), "cse")
+    assert st_e["cost_extracted"] <= st_g["cost_extracted"]
+    assert st_e["ops"] <= len(taps)
+    d = plain.to_dict()
+    load, params = rational_inputs(d, idx)
+    want = eval_rpn(d, load, params)
+    assert eval_ssa(ssa_e, load, params) == want and eval_ssa(ssa_g, load, params) == want
