@@ -291,8 +291,7 @@ bool plain_tile_ok(Tile t) {
 // Saturated tiles: (TX, tile rows) -> (TX, BY thread rows, RY rows per thread)
 // Taller tiles cut the share of y-halo rows (8 per tile): 64 x 32 and 256 x 8
 // run ~6 % faster than 128 x 8 on a 512^3 grid; 1024-thread tiles with four
-// rows per thread spill, and full-row 512 x 4 tiles measured 9 % slower, so
-// neither is offered.
+// rows per thread spill and are not offered.
 #define W25_SAT_TILES(X) X(64, 4, 4, 1) X(64, 8, 4, 2) X(64, 16, 4, 4) X(64, 32, 8, 4) X(32, 8, 8, 1) \
     X(32, 16, 8, 2) X(128, 4, 4, 1) X(128, 8, 4, 2) X(128, 16, 8, 2) X(256, 4, 4, 1) X(256, 8, 4, 2)
 
