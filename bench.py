@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X published FP64 vector peak
 # Launch shapes come from the library's exhaustive autotuner at plan time
 # (outside the timed region), separately for each form.
 TUNE = "exhaustive"
@@ -126,6 +127,37 @@ def setup_workload(name, variant, dev, torch, synth, Plan, plan_kw=None):
                     iterations=T, bytes_per_update=16, kernel_tag=f"{name}_{variant}", source="heat.hip",
                     storage="f64")
         return plan, step, reset, pts * T, T, meta
+    if name == "generic":
+        w = synth.generic_box_workload()
+        n, r, T = w["n"], w["radius"], 4
+        plan = Plan("generic", n, variant=variant, dtype="f64", radius=r, coef=w["coef"], taps=w["taps"],
+                    cids=w["cids"], **pk)
+        u0 = synth.generic_input(n, r, "f64", stream=901)
+        f = [torch.tensor(u0, device=dev), torch.empty(u0.shape, dtype=torch.float64, device=dev)]
+        base = f[0].clone()
+        del u0
+
+        def step():
+            plan.run(f, iterations=T)
+            return plan.residual()
+
+        def reset():
+            f[0].copy_(base)
+
+        n_taps = len(w["taps"])
+        n_groups = len(set((t[2], c) for t, c in zip(w["taps"], w["cids"])))
+        # FP64 operations per point update: plain = one multiply and one add per
+        # tap (the first add absent); saturated = the taps of a group summed
+        # (n_taps - n_groups adds) and one FMA per group
+        if variant == "plain":
+            instr, flops = 2 * n_taps - 1, 2 * n_taps - 1
+        else:
+            instr, flops = n_taps, (n_taps - n_groups) + 2 * n_groups
+        meta = dict(workload=f"generic box stencil r={r}, {n_taps} taps, {len(w['coef'])} shared coefficients "
+                             f"(symmetric), FP64, interior {n}, {T} sweeps + residual", interior=list(n),
+                    iterations=T, bytes_per_update=16, kernel_tag=f"generic_box3_{variant}", source="generic.hip",
+                    storage="f64", bound="alu", flops_per_update=flops, instr_per_update=instr)
+        return plan, step, reset, n[0] * n[1] * n[2] * T, T, meta
     if name == "batch":
         from paper_2306_13002_amd.stencil import BatchPlan
         sizes = synth.heat3d7_batch_sizes()
@@ -271,6 +303,19 @@ def cpu_baseline(name):
         dt = time.perf_counter() - t
         return dict(value=128 ** 3 * k / dt, unit="grid-point updates/s", cores=1, kind="oracle",
                     sample=f"128^3 crop of the same recipe, {k} steps, {dt:.1f} s, single thread")
+    if name == "generic":
+        w = synth.generic_box_workload()
+        n = (64, 64, 64)
+        u0 = synth.generic_input(n, w["radius"], "f64", stream=901)
+        t = time.perf_counter()
+        oracle.generic(u0, w["radius"], w["taps"], w["cids"], w["coef"], 1)
+        one = time.perf_counter() - t
+        k = max(1, min(200, int(20.0 / max(one, 1e-3))))
+        t = time.perf_counter()
+        oracle.generic(u0, w["radius"], w["taps"], w["cids"], w["coef"], k)
+        dt = time.perf_counter() - t
+        return dict(value=64 ** 3 * k / dt, unit="grid-point updates/s", cores=1, kind="oracle",
+                    sample=f"64^3 crop of the same recipe, {k} sweeps, {dt:.1f} s, single thread")
     u0 = synth.heat3d7_input(96, 96, 96) if name == "heat3d7" else synth.heat2d5_input(256)
     t = time.perf_counter()
     k = 20
@@ -378,7 +423,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="poisson19", choices=["poisson19", "wave25", "heat2d5", "heat3d7", "batch", "copy", "lhs"])
+    ap.add_argument("--workload", default="poisson19", choices=["poisson19", "wave25", "heat2d5", "heat3d7", "batch", "copy", "lhs", "generic"])
     ap.add_argument("--variant", default="best", choices=["best", "saturated", "saturated_t2", "plain"],
                     help="best: every saturated form the workload offers, tuned, the fastest reported")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain form beside it")
@@ -417,6 +462,26 @@ def main():
     alg_bytes = meta["bytes_per_update"] * pts_per_sweep  # one pass over the grid per launch
     achieved = alg_bytes / launch_s / 1e9
     traffic = read_traffic(meta["kernel_tag"], meta["source"])
+    roof = {
+        "bound": "hbm",
+        "kernel": meta["kernel_tag"],
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": alg_bytes,
+    }
+    if meta.get("bound") == "alu":
+        # FP64 vector peak: 256 CUs x 2.4 GHz x 128 FP64 flops per clock (64 FMA lanes) = 78.6 TFLOP/s, i.e.
+        # 39.3e12 FP64 instructions/s (an add issues like an FMA but counts one flop)
+        fl = meta["flops_per_update"] * pts_per_sweep / launch_s / 1e12
+        ins = meta["instr_per_update"] * pts_per_sweep / launch_s
+        roof = {"bound": "alu", "kernel": meta["kernel_tag"], "achieved": fl, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": fl / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                "algorithmic_flops_per_launch": meta["flops_per_update"] * pts_per_sweep,
+                "fp64_instr_per_s": ins, "issue_frac": ins / (FP64_VECTOR_PEAK_TFLOPS * 1e12 / 2),
+                "hbm_gbs": alg_bytes / launch_s / 1e9}
     out = {
         "metric": "grid-point updates/s (+ % of HBM peak), saturated vs plain",
         "value": value,
@@ -443,14 +508,7 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": {
-            "bound": "hbm",
-            "kernel": meta["kernel_tag"],
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": alg_bytes,
+            **roof,
             "avg_launch_us": launch_s * 1e6,
             "median_launch_us": main_r["sweep_ms_median"] * 1e3 * per_launch,
             "best_launch_us": main_r["sweep_ms_best"] * 1e3 * per_launch,
@@ -467,7 +525,7 @@ def main():
         pr = time_variant(a.workload, "plain", a.steps, a.warmup, dev, torch, synth, Plan)
         pv = pr["pts"] * a.steps / pr["wall"]
         pl = pr["sweep_ms"] / 1000.0 / max(1, pr["sweeps"])
-        out["plain"] = {"value": pv, "ms_per_step": pr["wall"] * 1000.0 / a.steps,
+        out["plain"] = {"value": pv, "ms_per_step": pr["wall"] * 1000.0 / a.steps, "us_per_sweep": pl * 1e6,
                         "achieved_gbs": meta["bytes_per_update"] * pts_per_sweep / pl / 1e9, "avg_launch_us": pl * 1e6,
                         "tile": list(pr["cfg"]["tile"]), "tile_map": pr["cfg"].get("tile_map")}
         out["saturated_over_plain"] = value / pv

@@ -370,3 +370,19 @@ def random_program(index: int, seed: int = 13, n_inputs: int = 4, n_outputs: int
         ins.append((_STORE, o, 0, 0, 0))
     return dict(n_inputs=n_inputs, n_outputs=n_outputs, n_params=n_params, n_locals=0, radius=radius, insns=ins,
                 consts=consts)
+
+
+# A VALU-bound generic stencil for measurement: FP64 box of radius 3 (343 taps)
+# with the fully symmetric sharing pattern (one coefficient per sorted |delta|
+# triple: 20 ids), coefficients U(0.1, 1) per id (seed 5, stream 900)
+# normalized to sum 1 over the taps, on a 256^3 interior, 4 sweeps.
+GENERIC_BOX_N = (256, 256, 256)
+
+
+def generic_box_workload(r: int = 3):
+    taps = box_taps(r)
+    cids, m = sharing_ids(taps, "symmetric", iter(()))
+    u = uniform_f64(5, 900, (m,))
+    vals = [0.1 + 0.9 * float(v) for v in u]
+    total = sum(vals[c] for c in cids)
+    return dict(radius=r, taps=taps, cids=cids, coef=[v / total for v in vals], dtype="f64", n=GENERIC_BOX_N)

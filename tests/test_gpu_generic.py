@@ -158,3 +158,25 @@ def test_table_driven_fallback_matches_oracle(tmp_path):
     assert r.returncode == 0, r.stderr
     errs = json.loads([l for l in r.stdout.splitlines() if l.startswith("ERR")][0][4:])
     assert all(e <= 1e-5 for e in errs)
+
+
+@pytest.mark.parametrize("variant", ["plain", "saturated"])
+def test_generic_box_workload_full_size_crops(dev, variant):
+    """The benchmark's VALU-bound generic workload (box r = 3, 343 taps, 20
+    shared coefficients, FP64, 256^3) at a tuned launch shape; after T = 2
+    sweeps a crop with a 3(T-1) margin around a region reproduces the
+    full-grid result exactly, so the oracle runs on crops."""
+    from gpu_util import compare_region, crop_box
+    w = synth.generic_box_workload()
+    n, r, T = w["n"], w["radius"], 2
+    st = dict(w, u0=synth.generic_input(n, r, "f64", stream=901))
+    got, gr, cfg = run(st, dev, T, variant=variant, tune="exhaustive")
+    assert cfg["variant"] == variant
+    tol = 0.0 if variant == "plain" else 1e-12
+    for lo, hi in [((0, 0, 0), (10, 9, 8)), ((120, 125, 130), (131, 133, 139)), ((246, 0, 248), (256, 7, 256))]:
+        sl, off = crop_box(n, lo, hi, r, r * (T - 1))
+        ref, _ = oracle.generic(st["u0"][sl], r, w["taps"], w["cids"], w["coef"], T)
+        gsl = tuple(slice(s.start + o0 + r, s.start + o1 + r) for s, (o0, o1) in zip(sl, off))
+        assert maxrel(got[gsl], compare_region(ref, off, r)) <= tol
+    assert np.array_equal(got[:r], st["u0"][:r])
+    assert np.isfinite(gr) and gr > 0
