@@ -39,7 +39,14 @@
  *                 before their first use;
  *   SAT_CSE_SAT   CSE after equality saturation (rules + extraction);
  *   SAT_CSE_BULK  CSE with every load hoisted to the start (bulk load);
- *   SAT_ACCSAT    saturation and bulk load together (the paper's default).
+ *   SAT_ACCSAT    saturation and bulk load together (the paper's default);
+ *   SAT_ACCSAT_Z  ACCSAT's arithmetic with the loads reused along z: a
+ *                 thread walks `zblock` planes of its (i, j) column; each
+ *                 load enters a register window of its (array, dx, dy)
+ *                 column one plane ahead and is reused while its z offset
+ *                 moves through the window (the MI355X counterpart of the
+ *                 stencil kernels' register queues).  Bit-identical to
+ *                 SAT_ACCSAT.
  * SAT_PLAIN and SAT_CSE evaluate exactly the written operations and are
  * bitwise reproducible against a plain FP64 evaluation; the saturated forms
  * reassociate and fuse (each fma rounds once).
@@ -94,7 +101,7 @@ typedef struct {
     int64_t pitch_y, pitch_z; /* elements; 0 = dense */
 } sat_program_desc;
 
-typedef enum { SAT_PLAIN = 0, SAT_CSE = 1, SAT_CSE_SAT = 2, SAT_CSE_BULK = 3, SAT_ACCSAT = 4 } sat_form;
+typedef enum { SAT_PLAIN = 0, SAT_CSE = 1, SAT_CSE_SAT = 2, SAT_CSE_BULK = 3, SAT_ACCSAT = 4, SAT_ACCSAT_Z = 5 } sat_form;
 
 /* Extraction: SAT_EXTRACT_GREEDY = bottom-up tree cost, then a DAG-cost local
  * search (common e-classes counted once); SAT_EXTRACT_EXACT = exhaustive
@@ -121,12 +128,14 @@ typedef struct {
  * "set <l> v<N>" per statement in order.  E_INVAL if a buffer is too small
  * (the message gives the size needed). */
 stencil_status sat_generate(const sat_program_desc *d, int32_t form, int32_t extract, int32_t tile_x, int32_t tile_y,
-                            char *src, int64_t src_len, char *ssa, int64_t ssa_len, sat_stats *stats);
+                            int32_t zblock, char *src, int64_t src_len, char *ssa, int64_t ssa_len, sat_stats *stats);
 
 /* Rewrite, generate and compile (hipRTC) the program for one form; one
- * thread per interior point, blocks of tile_x * tile_y threads (0 = 64 x 4)
- * over x, y and one z plane. */
-stencil_status sat_plan(const sat_program_desc *d, int32_t form, int32_t tile_x, int32_t tile_y, sat_plan_t *out);
+ * thread per interior (i, j) column, blocks of tile_x * tile_y threads (0 =
+ * 64 x 4) over x and y and one z plane -- or, for SAT_ACCSAT_Z, `zblock`
+ * planes per thread (0 = 32; ignored by the other forms). */
+stencil_status sat_plan(const sat_program_desc *d, int32_t form, int32_t tile_x, int32_t tile_y, int32_t zblock,
+                        sat_plan_t *out);
 
 /* Run the program once over the interior.  inputs: n_inputs device
  * pointers; outputs: n_outputs device pointers; params: n_params HOST

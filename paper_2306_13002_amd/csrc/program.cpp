@@ -23,7 +23,7 @@ using namespace stn;
 
 struct sat_plan_s {
     sat::Program prog;
-    int form = 0, tx = 64, ty = 4, device = 0;
+    int form = 0, tx = 64, ty = 4, zb = 1, device = 0;
     hipFunction_t fn = nullptr;
     long long span = 0;  // elements of one padded array
     bool profiling = false, prof_valid = false;
@@ -58,8 +58,11 @@ stencil_status read_desc(const sat_program_desc *d, sat::Program *p) {
     return STENCIL_OK;
 }
 
-stencil_status check_shape(const sat::Program &p, int form, int *tx, int *ty) {
-    if (form < SAT_PLAIN || form > SAT_ACCSAT) return fail(STENCIL_E_INVAL, "form %d is not a sat_form", form);
+stencil_status check_shape(const sat::Program &p, int form, int *tx, int *ty, int *zb) {
+    if (form < SAT_PLAIN || form > SAT_ACCSAT_Z) return fail(STENCIL_E_INVAL, "form %d is not a sat_form", form);
+    if (*zb < 0) return fail(STENCIL_E_INVAL, "zblock must be >= 0");
+    if (form != SAT_ACCSAT_Z) *zb = 1;
+    else if (*zb == 0) *zb = 32;
     if (*tx == 0 && *ty == 0) {
         *tx = 64;
         *ty = 4;
@@ -67,7 +70,7 @@ stencil_status check_shape(const sat::Program &p, int form, int *tx, int *ty) {
     const long long nt = (long long)*tx * *ty;
     if (*tx < 1 || *ty < 1 || nt % 64 != 0 || nt > 1024)
         return fail(STENCIL_E_INVAL, "block %d x %d: threads must be a multiple of 64, at most 1024", *tx, *ty);
-    if ((p.n[1] + *ty - 1) / *ty > 65535 || p.n[2] > 65535)
+    if ((p.n[1] + *ty - 1) / *ty > 65535 || (p.n[2] + *zb - 1) / *zb > 65535)
         return fail(STENCIL_E_UNSUPPORTED, "grid too large for one launch (y blocks and z extent must be <= 65535)");
     return STENCIL_OK;
 }
@@ -77,17 +80,17 @@ stencil_status check_shape(const sat::Program &p, int form, int *tx, int *ty) {
 extern "C" {
 
 stencil_status sat_generate(const sat_program_desc *d, int32_t form, int32_t extract, int32_t tile_x, int32_t tile_y,
-                            char *src, int64_t src_len, char *ssa, int64_t ssa_len, sat_stats *stats) {
+                            int32_t zblock, char *src, int64_t src_len, char *ssa, int64_t ssa_len, sat_stats *stats) {
     sat::Program p;
     stencil_status st = read_desc(d, &p);
     if (st != STENCIL_OK) return st;
-    int tx = tile_x, ty = tile_y;
-    if ((st = check_shape(p, form, &tx, &ty)) != STENCIL_OK) return st;
+    int tx = tile_x, ty = tile_y, zb = zblock;
+    if ((st = check_shape(p, form, &tx, &ty, &zb)) != STENCIL_OK) return st;
     if (extract != SAT_EXTRACT_GREEDY && extract != SAT_EXTRACT_EXACT)
         return fail(STENCIL_E_INVAL, "extract must be SAT_EXTRACT_GREEDY or SAT_EXTRACT_EXACT");
     sat::Generated g;
     bool unsupported = false;
-    const std::string err = sat::generate(p, form, extract, tx, ty, sat::Limits{}, &g, &unsupported);
+    const std::string err = sat::generate(p, form, extract, tx, ty, zb, sat::Limits{}, &g, &unsupported);
     if (!err.empty()) return fail(unsupported ? STENCIL_E_UNSUPPORTED : STENCIL_E_INVAL, "%s", err.c_str());
     if (src && (int64_t)g.src.size() + 1 > src_len)
         return fail(STENCIL_E_INVAL, "source buffer too small: %zu bytes needed", g.src.size() + 1);
@@ -111,19 +114,20 @@ stencil_status sat_generate(const sat_program_desc *d, int32_t form, int32_t ext
     return STENCIL_OK;
 }
 
-stencil_status sat_plan(const sat_program_desc *d, int32_t form, int32_t tile_x, int32_t tile_y, sat_plan_t *out) {
+stencil_status sat_plan(const sat_program_desc *d, int32_t form, int32_t tile_x, int32_t tile_y, int32_t zblock,
+                        sat_plan_t *out) {
     if (!out) return fail(STENCIL_E_INVAL, "out is NULL");
     *out = nullptr;
     sat::Program p;
     stencil_status st = read_desc(d, &p);
     if (st != STENCIL_OK) return st;
-    int tx = tile_x, ty = tile_y;
-    if ((st = check_shape(p, form, &tx, &ty)) != STENCIL_OK) return st;
+    int tx = tile_x, ty = tile_y, zb = zblock;
+    if ((st = check_shape(p, form, &tx, &ty, &zb)) != STENCIL_OK) return st;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(STENCIL_E_DEVICE, "no HIP device");
     sat::Generated g;
     bool unsupported = false;
-    const std::string err = sat::generate(p, form, SAT_EXTRACT_GREEDY, tx, ty, sat::Limits{}, &g, &unsupported);
+    const std::string err = sat::generate(p, form, SAT_EXTRACT_GREEDY, tx, ty, zb, sat::Limits{}, &g, &unsupported);
     if (!err.empty()) return fail(STENCIL_E_INVAL, "%s", err.c_str());
     logf("saturator form %d: %d e-nodes, %d e-classes, %d iterations, cost %.0f -> %.0f, %d loads %d ops", form,
          g.st.enodes, g.st.eclasses, g.st.iterations, g.st.cost_input, g.st.cost_extracted, g.st.loads, g.st.ops);
@@ -135,6 +139,7 @@ stencil_status sat_plan(const sat_program_desc *d, int32_t form, int32_t tile_x,
     pl->form = form;
     pl->tx = tx;
     pl->ty = ty;
+    pl->zb = zb;
     pl->fn = fn;
     (void)hipGetDevice(&pl->device);
     const sat::Program &q = pl->prog;
@@ -189,7 +194,7 @@ stencil_status sat_run(sat_plan_t p, const void *const *inputs, void *const *out
     if (p->profiling) e = hipEventRecord(p->ev0, s);
     if (e == hipSuccess)
         e = hipModuleLaunchKernel(p->fn, (unsigned)((q.n[0] + p->tx - 1) / p->tx), (unsigned)((q.n[1] + p->ty - 1) / p->ty),
-                                  (unsigned)q.n[2], p->tx, p->ty, 1, 0, s, nullptr, extra);
+                                  (unsigned)((q.n[2] + p->zb - 1) / p->zb), p->tx, p->ty, 1, 0, s, nullptr, extra);
     if (e == hipSuccess && p->profiling) e = hipEventRecord(p->ev1, s);
     if (cur != p->device) (void)hipSetDevice(cur);
     if (e != hipSuccess) return hip_fail(e, "saturator kernel launch");

@@ -582,15 +582,30 @@ std::string hexd(double v) {
     return v < 0 ? "(" + std::string(b) + ")" : std::string(b);
 }
 
+// A column of the z-streaming form: the loads of one array at one (dx, dy),
+// kept in registers w<c>_0 .. w<c>_<dz1-dz0> for z offsets dz0 .. dz1.
+struct Column {
+    int a, dx, dy, dz0, dz1;
+};
+
 struct Emitter {
     const Program &p;
     std::string body, ssa;
     int next = 0;
     int loads = 0, ops = 0, fmas = 0;
+    bool stream = false;          // loads read the z-streaming window registers
+    std::vector<Column> cols;     // stream: the columns, in load order
 
     long long offset(int dx, int dy, int dz) const { return (long long)dz * p.pz + (long long)dy * p.py + dx; }
     std::string load_expr(int a, int dx, int dy, int dz) const {
         char b[96];
+        if (stream) {
+            for (size_t c = 0; c < cols.size(); ++c)
+                if (cols[c].a == a && cols[c].dx == dx && cols[c].dy == dy) {
+                    std::snprintf(b, sizeof b, "w%zu_%d", c, dz - cols[c].dz0);
+                    return b;
+                }
+        }
         std::snprintf(b, sizeof b, "A.in[%d][o + (%lldLL)]", a, offset(dx, dy, dz));
         return b;
     }
@@ -799,6 +814,19 @@ void gen_selected(const Program &p, EGraph &g, const std::vector<int> &sel, cons
                 if (x.off[i] != y.off[i]) return x.off[i] < y.off[i];
             return false;
         });
+        if (E.stream) {  // one window per (array, dx, dy): the z range its loads span
+            for (int c : lc) {
+                const Node &n = g.nodes(c)[sel[c]];
+                bool found = false;
+                for (Column &col : E.cols)
+                    if (col.a == (int)n.pay && col.dx == n.off[0] && col.dy == n.off[1]) {
+                        col.dz0 = std::min(col.dz0, n.off[2]);
+                        col.dz1 = std::max(col.dz1, n.off[2]);
+                        found = true;
+                    }
+                if (!found) E.cols.push_back({(int)n.pay, n.off[0], n.off[1], n.off[2], n.off[2]});
+            }
+        }
         for (int c : lc) emit_one(c);
     }
     for (const Stmt &s : stmts) {
@@ -829,13 +857,13 @@ double written_cost(const Program &p) {
     return c;
 }
 
-const char *kFormName[] = {"PLAIN", "CSE", "CSE+SAT", "CSE+BULK", "ACCSAT"};
+const char *kFormName[] = {"PLAIN", "CSE", "CSE+SAT", "CSE+BULK", "ACCSAT", "ACCSAT + z streaming"};
 
 }  // namespace
 
 const char *kernel_name(int form) {
-    static const char *names[] = {"sat_kernel_plain", "sat_kernel_cse", "sat_kernel_cse_sat", "sat_kernel_cse_bulk",
-                                  "sat_kernel_accsat"};
+    static const char *names[] = {"sat_kernel_plain", "sat_kernel_cse",    "sat_kernel_cse_sat",
+                                  "sat_kernel_cse_bulk", "sat_kernel_accsat", "sat_kernel_accsat_z"};
     return names[form];
 }
 
@@ -940,8 +968,8 @@ std::string validate(Program &p) {
     return "";
 }
 
-std::string generate(const Program &p, int form, int extract, int tx, int ty, const Limits &lim, Generated *out,
-                     bool *unsupported) {
+std::string generate(const Program &p, int form, int extract, int tx, int ty, int zb, const Limits &lim,
+                     Generated *out, bool *unsupported) {
     *unsupported = false;
     Emitter E{p};
     Stats st;
@@ -950,8 +978,9 @@ std::string generate(const Program &p, int form, int extract, int tx, int ty, co
         gen_plain(p, E);
         st.cost_extracted = st.cost_input;
     } else {
-        const bool rules = form == F_CSE_SAT || form == F_ACCSAT;
-        const bool bulk = form == F_CSE_BULK || form == F_ACCSAT;
+        const bool rules = form == F_CSE_SAT || form == F_ACCSAT || form == F_ACCSAT_Z;
+        const bool bulk = form == F_CSE_BULK || form == F_ACCSAT || form == F_ACCSAT_Z;
+        E.stream = form == F_ACCSAT_Z;
         EGraph g(rules);
         std::vector<Stmt> stmts = load_program(p, g);
         const Clock::time_point t0 = Clock::now();
@@ -1015,17 +1044,66 @@ std::string generate(const Program &p, int form, int extract, int tx, int ty, co
     std::snprintf(b, sizeof b, "struct SatArgs {\n    const double *in[%d];\n    double *out[%d];\n    double prm[%d];\n};\n",
                   NI, p.n_out, NP);
     s += b;
-    std::snprintf(b, sizeof b,
-                  "extern \"C\" __global__ __launch_bounds__(%d) void %s(SatArgs A) {\n"
-                  "    const int i = (int)(blockIdx.x * %d + threadIdx.x);\n"
-                  "    const int j = (int)(blockIdx.y * %d + threadIdx.y);\n"
-                  "    const int k = (int)blockIdx.z;\n"
-                  "    if (i >= %lld || j >= %lld) return;\n"
-                  "    const long long o = (long long)(k + %d) * %lldLL + (long long)(j + %d) * %lldLL + (i + %d);\n",
-                  tx * ty, kernel_name(form), tx, ty, p.n[0], p.n[1], p.radius, p.pz, p.radius, p.py, p.radius);
-    s += b;
-    s += E.body;
-    s += "}\n";
+    if (form != F_ACCSAT_Z) {
+        std::snprintf(b, sizeof b,
+                      "extern \"C\" __global__ __launch_bounds__(%d) void %s(SatArgs A) {\n"
+                      "    const int i = (int)(blockIdx.x * %d + threadIdx.x);\n"
+                      "    const int j = (int)(blockIdx.y * %d + threadIdx.y);\n"
+                      "    const int k = (int)blockIdx.z;\n"
+                      "    if (i >= %lld || j >= %lld) return;\n"
+                      "    const long long o = (long long)(k + %d) * %lldLL + (long long)(j + %d) * %lldLL + (i + %d);\n",
+                      tx * ty, kernel_name(form), tx, ty, p.n[0], p.n[1], p.radius, p.pz, p.radius, p.py, p.radius);
+        s += b;
+        s += E.body;
+        s += "}\n";
+    } else {
+        // z streaming: a thread walks planes k0 .. k1-1 of its (i, j) column;
+        // every load enters a register window at its column's highest z
+        // offset and moves down one register per plane until it leaves at
+        // the lowest offset.
+        std::snprintf(b, sizeof b,
+                      "extern \"C\" __global__ __launch_bounds__(%d) void %s(SatArgs A) {\n"
+                      "    const int i = (int)(blockIdx.x * %d + threadIdx.x);\n"
+                      "    const int j = (int)(blockIdx.y * %d + threadIdx.y);\n"
+                      "    const int k0 = (int)blockIdx.z * %d, k1 = k0 + %d < %lld ? k0 + %d : %lld;\n"
+                      "    if (i >= %lld || j >= %lld) return;\n"
+                      "    long long o = (long long)(k0 + %d) * %lldLL + (long long)(j + %d) * %lldLL + (i + %d);\n",
+                      tx * ty, kernel_name(form), tx, ty, zb, zb, p.n[2], zb, p.n[2], p.n[0], p.n[1], p.radius, p.pz,
+                      p.radius, p.py, p.radius);
+        s += b;
+        for (size_t c = 0; c < E.cols.size(); ++c) {
+            const Column &col = E.cols[c];
+            for (int d = 0; d <= col.dz1 - col.dz0; ++d) {
+                std::snprintf(b, sizeof b, "    double w%zu_%d = A.in[%d][o + (%lldLL)];\n", c, d, col.a,
+                              E.offset(col.dx, col.dy, col.dz0 + d));
+                s += b;
+            }
+        }
+        // The window holds every live value (no separate prefetch registers:
+        // with many columns the windows alone fill the register file); the
+        // next plane's loads are issued right after the shift, as the last
+        // statements of a step, and awaited at their first use.
+        s += "    for (int k = k0; k < k1; ++k) {\n";
+        size_t pos = 0;
+        while (pos < E.body.size()) {
+            const size_t e = E.body.find('\n', pos);
+            s += "    " + E.body.substr(pos, e - pos + 1);
+            pos = e + 1;
+        }
+        s += "        if (k + 1 < k1) {\n";
+        for (size_t c = 0; c < E.cols.size(); ++c) {
+            const Column &col = E.cols[c];
+            for (int d = 0; d < col.dz1 - col.dz0; ++d) {
+                std::snprintf(b, sizeof b, "            w%zu_%d = w%zu_%d;\n", c, d, c, d + 1);
+                s += b;
+            }
+            std::snprintf(b, sizeof b, "            w%zu_%d = A.in[%d][o + (%lldLL)];\n", c, col.dz1 - col.dz0, col.a,
+                          E.offset(col.dx, col.dy, col.dz1 + 1));
+            s += b;
+        }
+        std::snprintf(b, sizeof b, "        }\n        o += %lldLL;\n    }\n}\n", p.pz);
+        s += b;
+    }
     out->src = s;
     out->ssa = E.ssa;
     out->st = st;

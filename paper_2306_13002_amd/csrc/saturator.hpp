@@ -46,7 +46,7 @@ struct Generated {
     Stats st;
 };
 
-enum Form { F_PLAIN = 0, F_CSE = 1, F_CSE_SAT = 2, F_CSE_BULK = 3, F_ACCSAT = 4 };
+enum Form { F_PLAIN = 0, F_CSE = 1, F_CSE_SAT = 2, F_CSE_BULK = 3, F_ACCSAT = 4, F_ACCSAT_Z = 5 };
 
 // Limits of the saturation (the paper's Sec. Evaluation settings).
 struct Limits {
@@ -62,11 +62,12 @@ const char *kernel_name(int form);
 // Check a program; returns "" or the reason it is rejected.
 std::string validate(Program &p);
 
-// Rewrite (forms 2 and 4), extract and generate HIP source for one form.
-// extract: 0 greedy + DAG local search, 1 exhaustive.  Returns "" or an
-// error text; `unsupported` is set when the exhaustive extraction is too big.
-std::string generate(const Program &p, int form, int extract, int tx, int ty, const Limits &lim, Generated *out,
-                     bool *unsupported);
+// Rewrite (forms 2, 4, 5), extract and generate HIP source for one form.
+// extract: 0 greedy + DAG local search, 1 exhaustive; zb: z planes per
+// thread of the streaming form.  Returns "" or an error text; `unsupported`
+// is set when the exhaustive extraction is too big.
+std::string generate(const Program &p, int form, int extract, int tx, int ty, int zb, const Limits &lim,
+                     Generated *out, bool *unsupported);
 
 }  // namespace sat
 }  // namespace stn

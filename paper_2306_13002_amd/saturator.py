@@ -21,7 +21,7 @@ from typing import Optional, Sequence
 from . import stencil as S
 
 OP_CONST, OP_PARAM, OP_LOAD, OP_ADD, OP_SUB, OP_MUL, OP_NEG, OP_STORE, OP_SET, OP_GET = range(1, 11)
-FORMS = {"plain": 0, "cse": 1, "cse_sat": 2, "cse_bulk": 3, "accsat": 4}
+FORMS = {"plain": 0, "cse": 1, "cse_sat": 2, "cse_bulk": 3, "accsat": 4, "accsat_z": 5}
 FORM_NAMES = {v: k for k, v in FORMS.items()}
 EXTRACT = {"greedy": 0, "exact": 1}
 
@@ -207,8 +207,10 @@ def _lib():
     if not getattr(L, "_sat_sigs", False):
         P = ctypes.POINTER
         L.sat_generate.argtypes = [P(SatProgramDesc), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                   ctypes.c_char_p, ctypes.c_int64, ctypes.c_char_p, ctypes.c_int64, P(SatStats)]
-        L.sat_plan.argtypes = [P(SatProgramDesc), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_void_p)]
+                                   ctypes.c_int32, ctypes.c_char_p, ctypes.c_int64, ctypes.c_char_p, ctypes.c_int64,
+                                   P(SatStats)]
+        L.sat_plan.argtypes = [P(SatProgramDesc), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                               P(ctypes.c_void_p)]
         L.sat_run.argtypes = [ctypes.c_void_p, P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_double),
                               ctypes.c_void_p]
         L.sat_plan_info.argtypes = [ctypes.c_void_p, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]
@@ -231,7 +233,7 @@ def _as_program(prog) -> Program:
 
 
 def generate(prog, n: Sequence[int], form: str = "accsat", extract: str = "greedy",
-             tile: Sequence[int] = (0, 0), pitch: Sequence[int] = (0, 0)):
+             tile: Sequence[int] = (0, 0), pitch: Sequence[int] = (0, 0), zblock: int = 0):
     """Rewrite and generate on the host: (HIP source, SSA text, stats dict).
     prog: a Program or its dict form."""
     d, keep = _as_program(prog).desc(n, pitch)
@@ -241,8 +243,8 @@ def generate(prog, n: Sequence[int], form: str = "accsat", extract: str = "greed
         src = ctypes.create_string_buffer(size)
         ssa = ctypes.create_string_buffer(size)
         st = SatStats()
-        r = L.sat_generate(ctypes.byref(d), FORMS[form], EXTRACT[extract], int(tile[0]), int(tile[1]), src, size,
-                           ssa, size, ctypes.byref(st))
+        r = L.sat_generate(ctypes.byref(d), FORMS[form], EXTRACT[extract], int(tile[0]), int(tile[1]), int(zblock),
+                           src, size, ssa, size, ctypes.byref(st))
         if r == S.OK:
             del keep
             return src.value.decode(), ssa.value.decode(), _stats(st)
@@ -256,11 +258,12 @@ class ProgramPlan:
     """A program compiled for one form; run() takes torch tensors."""
 
     def __init__(self, prog, n: Sequence[int], form: str = "accsat", tile: Sequence[int] = (0, 0),
-                 pitch: Sequence[int] = (0, 0)):
+                 pitch: Sequence[int] = (0, 0), zblock: int = 0):
         self.prog, self.form = _as_program(prog), form
         d, keep = self.prog.desc(n, pitch)
         h = ctypes.c_void_p()
-        S._check(_lib().sat_plan(ctypes.byref(d), FORMS[form], int(tile[0]), int(tile[1]), ctypes.byref(h)))
+        S._check(_lib().sat_plan(ctypes.byref(d), FORMS[form], int(tile[0]), int(tile[1]), int(zblock),
+                                 ctypes.byref(h)))
         del keep
         self._h = h
 

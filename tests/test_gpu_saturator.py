@@ -19,7 +19,7 @@ from gpu_util import maxrel
 
 pytestmark = pytest.mark.gpu
 
-FORMS = ["plain", "cse", "cse_sat", "cse_bulk", "accsat"]
+FORMS = ["plain", "cse", "cse_sat", "cse_bulk", "accsat", "accsat_z"]
 EXACT = {"plain", "cse", "cse_bulk"}
 TOL = 1e-12
 
@@ -28,10 +28,10 @@ def dev(a):
     return torch.tensor(a, dtype=torch.float64, device="cuda")
 
 
-def run(prog, n, ins_dev, params, form, tile=(0, 0), shape=None, pitch=(0, 0)):
+def run(prog, n, ins_dev, params, form, tile=(0, 0), shape=None, pitch=(0, 0), zblock=0):
     shape = shape or tuple(ins_dev[0].shape)
     outs = [torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(prog["n_outputs"])]
-    plan = X.ProgramPlan(prog, n, form, tile=tile, pitch=pitch)
+    plan = X.ProgramPlan(prog, n, form, tile=tile, pitch=pitch, zblock=zblock)
     plan.run(ins_dev, outs, params)
     torch.cuda.synchronize()
     plan.close()
@@ -76,6 +76,37 @@ def test_random_programs(idx, form):
     check(form, got, want, 1)
 
 
+@pytest.mark.parametrize("zb", [1, 3, 4, 11, 64])
+def test_z_streaming_equals_accsat_bitwise(zb):
+    """Reusing loads along z changes where values come from, not the
+    arithmetic: every z-block depth (ragged against nz = 11) gives ACCSAT's
+    result bit for bit."""
+    prog = synth.lhs_program()
+    n = (37, 13, 11)
+    d = [dev(a) for a in synth.lhs_inputs(n)]
+    base = run(prog, n, d, synth.LHS_PARAMS, "accsat")
+    got = run(prog, n, d, synth.LHS_PARAMS, "accsat_z", zblock=zb)
+    for g, b in zip(got, base):
+        assert np.array_equal(g, b)
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_z_streaming_random_programs_with_radius_two(idx):
+    """Programs reading z offsets -2..2 (windows of up to five planes)."""
+    prog = synth.random_program(200 + idx, radius=2)
+    n = (21, 6, 9)
+    shape = (n[2] + 4, n[1] + 4, n[0] + 4)
+    ins = [synth.uniform_f64(47, s, shape) + 0.5 for s in range(prog["n_inputs"])]
+    params = [0.5, 1.25, 2.0]
+    want = oracle.program(prog, ins, params, n)
+    d = [dev(a) for a in ins]
+    got = run(prog, n, d, params, "accsat_z", zblock=4)
+    check("accsat_z", got, want, 2)
+    base = run(prog, n, d, params, "accsat")
+    for g, b in zip(got, base):
+        assert np.array_equal(g, b)
+
+
 @pytest.mark.parametrize("tile", [(64, 4), (128, 2), (256, 1), (32, 8), (64, 16), (1024, 1)])
 def test_block_shapes_agree_bitwise(tile):
     prog = synth.lhs_program()
@@ -111,7 +142,7 @@ def test_pitched_arrays():
         assert not np.any(g2)  # padding and halo untouched (zero-initialized)
 
 
-@pytest.mark.parametrize("form", ["plain", "accsat"])
+@pytest.mark.parametrize("form", ["plain", "accsat", "accsat_z"])
 def test_lhs_full_size_sampled_slabs(form):
     """The 162^3 workload at the benchmark's launch shape; the outputs of a
     point depend only on planes k-1..k+1, so the oracle runs on z-slabs of

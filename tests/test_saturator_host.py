@@ -23,7 +23,7 @@ from paper_2306_13002_amd import stencil as S
 from paper_2306_13002_amd import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-FORMS = ["plain", "cse", "cse_sat", "cse_bulk", "accsat"]
+FORMS = ["plain", "cse", "cse_sat", "cse_bulk", "accsat", "accsat_z"]
 
 
 def header_symbols():
@@ -44,7 +44,7 @@ def test_desc_struct_size_checked():
     p = synth.lhs_program()
     d, keep = X.Program.from_dict(p).desc((8, 8, 8))
     d.struct_size -= 8
-    st = X._lib().sat_generate(ctypes.byref(d), 0, 0, 0, 0, None, 0, None, 0, None)
+    st = X._lib().sat_generate(ctypes.byref(d), 0, 0, 0, 0, 0, None, 0, None, 0, None)
     assert st == S.E_INVAL and "struct_size" in S.last_error()
 
 
