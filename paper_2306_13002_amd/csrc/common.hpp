@@ -149,10 +149,12 @@ struct HaloStager {
 #pragma unroll
         for (int s = 0; s < HR; ++s) val[s] = ok[s] ? plane[goff[s]] : T(0);
     }
-    __device__ __forceinline__ void store(T *lds) const {
+    // L: the LDS element type (a wider type widens exactly on store)
+    template <typename L>
+    __device__ __forceinline__ void store(L *lds) const {
 #pragma unroll
         for (int s = 0; s < HR; ++s)
-            if (has[s]) lds[lidx[s]] = val[s];
+            if (has[s]) lds[lidx[s]] = (L)val[s];
     }
 };
 

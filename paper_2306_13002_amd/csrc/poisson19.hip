@@ -263,9 +263,9 @@ __global__ __launch_bounds__(TX *TY) void poisson19_sat(const float *__restrict_
 // planes zc-1, zc, zc+1 of an LDS tile of row width W) and the point's 12
 // coefficients; returns ss and the new value rounded to F32.  The same
 // operations in the same order as poisson19_sat.
-template <int W>
-__device__ __forceinline__ double p19_update(const float *m, const float *o, const float *u, int e, const float *cc,
-                                             double omega, float *out) {
+template <int W, typename L>
+__device__ __forceinline__ double p19_update(const L *m, const L *o, const L *u, int e, const float *cc, double omega,
+                                             float *out) {
     const double pc = o[e];
     const double pE = o[e + 1], pW = o[e - 1], pN = o[e + W], pS = o[e - W];
     const double B0v = ((double)o[e + W + 1] - (double)o[e - W + 1]) - ((double)o[e + W - 1] - (double)o[e - W - 1]);
@@ -297,14 +297,31 @@ __device__ __forceinline__ double p19_update(const float *m, const float *o, con
 // produce (same operations, sweep-1 values rounded to F32 as if stored), so
 // the result and the residual (sum of ss^2 of the second sweep) match it bit
 // for bit.  Cells of the ring that are boundary cells keep their fixed value.
+//
+// Threads: TY rows of TX "tile" threads (one output cell each: its sweep-1
+// and sweep-2 values) and EY extra rows of "ring" threads (one ring cell of
+// sweep 1 each), so that no wave carries two sweep-1 cells.
 template <int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void poisson19_sat2(const float *__restrict__ p, float *__restrict__ pn,
-                                                         P19Coef c, Geom g, double omega, int zb, int remap,
-                                                         double *__restrict__ part) {
+struct Sat2Shape {
+    static constexpr int W1 = TX + 2;
+    static constexpr int RS = 2 * W1 + 2 * TY;  // ring cells of the sweep-1 tile
+    static constexpr int EY0 = (RS + TX - 1) / TX;
+    static constexpr int EY = (TX * (TY + EY0)) % 64 == 0 ? EY0 : EY0 + 1;  // whole waves
+    static constexpr int NT = TX * (TY + EY);
+};
+
+template <int TX, int TY>
+__global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const float *__restrict__ p,
+                                                                         float *__restrict__ pn, P19Coef c, Geom g,
+                                                                         double omega, int zb, int remap,
+                                                                         double *__restrict__ part) {
+    using S = Sat2Shape<TX, TY>;
     constexpr int W0 = TX + 4, PL0 = (TY + 4) * W0;  // p^t tile, two-cell halo
-    constexpr int W1 = TX + 2, PL1 = (TY + 2) * W1;  // sweep-1 tile, one-cell ring
-    constexpr int NT = TX * TY, RS = 2 * W1 + 2 * TY;
-    static_assert(RS <= NT, "every ring cell needs a thread");
+    constexpr int W1 = S::W1, PL1 = (TY + 2) * W1;   // sweep-1 tile, one-cell ring
+    constexpr int NT = S::NT, RS = S::RS;
+    static_assert(RS <= TX * S::EY && NT <= 1024, "ring threads");
+    // The LDS rings hold the F32 values (widened at each read: FP64 rings
+    // double the LDS traffic and measured slower).
     __shared__ float r0[4][PL0];
     __shared__ float r1[4][PL1];
     __shared__ double red[kMaxWaves];
@@ -314,30 +331,37 @@ __global__ __launch_bounds__(TX *TY) void poisson19_sat2(const float *__restrict
     const int PX = g.nx + 2, PY = g.ny + 2;
     const int k0 = bz * zb, k1 = min(k0 + zb, g.nz);  // output planes zc = k0+1 .. k1 (padded)
 
-    // own cell: sweep-1 cell (tx+1, ty+1) of the ring tile, output cell of sweep 2
+    // tile thread: sweep-1 cell (tx+1, ty+1) of the ring tile and output cell of sweep 2
+    const bool tile_t = ty < TY;
     const int xo = bx * TX + tx + 1, yo = by * TY + ty + 1;  // padded coordinates
-    const bool in_o = xo <= g.nx && yo <= g.ny;
-    const bool ld_o = xo < PX && yo < PY;
+    const bool in_o = tile_t && xo <= g.nx && yo <= g.ny;
+    const bool ld_o = tile_t && xo < PX && yo < PY;
     const long long col_o = (long long)yo * g.py + xo;
     const int e0_o = (ty + 2) * W0 + tx + 2, e1_o = (ty + 1) * W1 + tx + 1;
-    // ring cell of the sweep-1 tile handled by this thread (tid < RS)
+    // ring thread: ring cell q of the sweep-1 tile
+    const int q = tid - TX * TY;
+    const bool has_r = !tile_t && q < RS;
     int ex = 0, ey = 0;
-    if (tid < W1) {
-        ex = tid;
-    } else if (tid < 2 * W1) {
-        ex = tid - W1;
+    if (q < W1) {
+        ex = q;
+    } else if (q < 2 * W1) {
+        ex = q - W1;
         ey = TY + 1;
-    } else if (tid < 2 * W1 + TY) {
-        ey = tid - 2 * W1 + 1;
+    } else if (q < 2 * W1 + TY) {
+        ey = q - 2 * W1 + 1;
     } else {
         ex = W1 - 1;
-        ey = tid - 2 * W1 - TY + 1;
+        ey = q - 2 * W1 - TY + 1;
     }
-    const bool has_r = tid < RS;
     const int xr = bx * TX + ex, yr = by * TY + ey;  // padded
     const bool in_r = has_r && xr >= 1 && xr <= g.nx && yr >= 1 && yr <= g.ny;
     const long long col_r = (long long)yr * g.py + xr;
     const int e0_r = (ey + 1) * W0 + ex + 1, e1_r = ey * W1 + ex;
+    // the cell this thread computes in sweep 1
+    const bool in_a = tile_t ? in_o : in_r;
+    const bool has_a = tile_t || has_r;
+    const long long col_a = tile_t ? col_o : col_r;
+    const int e0_a = tile_t ? e0_o : e0_r, e1_a = tile_t ? e1_o : e1_r;
 
     HaloStager<float, TX, TY, 2, true, NT> halo;
     halo.init(tid, bx * TX + 1, by * TY + 1, g.py, PX, PY);
@@ -347,25 +371,24 @@ __global__ __launch_bounds__(TX *TY) void poisson19_sat2(const float *__restrict
     for (int z = zlo - 1; z <= zlo; ++z) {
         if (z < 0) continue;
         const float *pl = p + (long long)z * g.pz;
-        r0[z & 3][e0_o] = ld_o ? pl[col_o] : 0.0f;
+        if (tile_t) r0[z & 3][e0_o] = ld_o ? pl[col_o] : 0.0f;
         halo.load(pl);
         halo.store(r0[z & 3]);
     }
     float ctr = ld_o ? p[col_o + (long long)(zlo + 1) * g.pz] : 0.0f;
     halo.load(p + (long long)(zlo + 1) * g.pz);
-    // coefficients of the sweep-1 plane about to be computed (own and ring
-    // cell), and of the own cell for the two planes before it (sweep 2 runs
-    // two planes behind sweep 1)
-    float cf_o[12], cf_r[12], c1_o[12], c2_o[12];
+    // coefficients of this thread's sweep-1 cell for the plane about to be
+    // computed, and (tile threads) of the own cell for the two planes before
+    // it: sweep 2 runs two planes behind sweep 1
+    float cf[12], c1[12], c2[12];
     {
         const bool zin = zlo >= 1 && zlo <= g.nz;
-        const long long qo = col_o + (long long)zlo * g.pz, qr = col_r + (long long)zlo * g.pz;
+        const long long qa = col_a + (long long)zlo * g.pz;
 #pragma unroll
         for (int s = 0; s < 12; ++s) {
-            cf_o[s] = (zin && in_o) ? c.f[s][qo] : 0.0f;
-            cf_r[s] = (zin && in_r) ? c.f[s][qr] : 0.0f;
-            c1_o[s] = 0.0f;
-            c2_o[s] = 0.0f;
+            cf[s] = (zin && in_a) ? c.f[s][qa] : 0.0f;
+            c1[s] = 0.0f;
+            c2[s] = 0.0f;
         }
     }
     double acc = 0.0;
@@ -374,15 +397,12 @@ __global__ __launch_bounds__(TX *TY) void poisson19_sat2(const float *__restrict
     // sweep-1 planes zA-3 .. zA-1, were written in earlier iterations), so one
     // barrier per plane separates every LDS write from its readers.
     for (int zA = zlo; zA <= zhi + 1; ++zA) {
-        float cc_o[12], cc_r[12];
+        float cc[12];
 #pragma unroll
-        for (int s = 0; s < 12; ++s) {
-            cc_o[s] = cf_o[s];
-            cc_r[s] = cf_r[s];
-        }
+        for (int s = 0; s < 12; ++s) cc[s] = cf[s];
         if (zA <= zhi) {
             // stage p^t plane zA+1, then issue every load of the next plane
-            r0[(zA + 1) & 3][e0_o] = ctr;
+            if (tile_t) r0[(zA + 1) & 3][e0_o] = ctr;
             halo.store(r0[(zA + 1) & 3]);
             if (zA < zhi) {
                 if (zA + 2 <= g.nz + 1) {
@@ -391,40 +411,32 @@ __global__ __launch_bounds__(TX *TY) void poisson19_sat2(const float *__restrict
                     halo.load(pl);
                 }
                 const bool zin = zA + 1 >= 1 && zA + 1 <= g.nz;
-                const long long qo = col_o + (long long)(zA + 1) * g.pz, qr = col_r + (long long)(zA + 1) * g.pz;
+                const long long qa = col_a + (long long)(zA + 1) * g.pz;
 #pragma unroll
-                for (int s = 0; s < 12; ++s) {
-                    cf_o[s] = (zin && in_o) ? c.f[s][qo] : 0.0f;
-                    cf_r[s] = (zin && in_r) ? c.f[s][qr] : 0.0f;
-                }
+                for (int s = 0; s < 12; ++s) cf[s] = (zin && in_a) ? c.f[s][qa] : 0.0f;
             }
         }
         __syncthreads();
-        if (zA <= zhi) {  // sweep 1 at plane zA on the tile and its ring
+        if (zA <= zhi && has_a) {  // sweep 1 at plane zA: own cell or ring cell
             const bool zin = zA >= 1 && zA <= g.nz;
             const float *m = r0[(zA - 1) & 3], *o = r0[zA & 3], *u = r0[(zA + 1) & 3];
             float v;
-            if (zin && in_o) p19_update<W0>(m, o, u, e0_o, cc_o, omega, &v);
-            else v = o[e0_o];
-            r1[zA & 3][e1_o] = v;
-            if (has_r) {
-                if (zin && in_r) p19_update<W0>(m, o, u, e0_r, cc_r, omega, &v);
-                else v = o[e0_r];
-                r1[zA & 3][e1_r] = v;
-            }
+            if (zin && in_a) p19_update<W0>(m, o, u, e0_a, cc, omega, &v);
+            else v = o[e0_a];
+            r1[zA & 3][e1_a] = v;
         }
         const int zc = zA - 2;  // sweep 2 at plane zc, from sweep-1 planes zc-1 .. zc+1
         if (zc >= k0 + 1 && in_o) {
             const float *m = r1[(zc - 1) & 3], *o = r1[zc & 3], *u = r1[(zc + 1) & 3];
             float v;
-            const double ss = p19_update<W1>(m, o, u, e1_o, c2_o, omega, &v);
+            const double ss = p19_update<W1>(m, o, u, e1_o, c2, omega, &v);
             pn[col_o + (long long)zc * g.pz] = v;
             acc = fma(ss, ss, acc);
         }
 #pragma unroll
         for (int s = 0; s < 12; ++s) {
-            c2_o[s] = c1_o[s];
-            c1_o[s] = cc_o[s];
+            c2[s] = c1[s];
+            c1[s] = cc[s];
         }
     }
     if (part) {
@@ -440,10 +452,10 @@ bool plain_tile_ok(Tile t) {
 
 #define P19_SAT_TILES(X) X(32, 2) X(32, 4) X(32, 8) X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(128, 1) X(128, 2) \
     X(128, 4) X(128, 8) X(256, 1) X(256, 4)
-// Two-sweep tiles: every cell of the one-cell ring around the tile needs a
-// thread (2(TX+2) + 2 TY <= TX TY); each is also a single-sweep tile (an odd
-// sweep count starts with one single sweep at the same shape).
-#define P19_SAT2_TILES(X) X(32, 4) X(32, 8) X(64, 4) X(64, 8) X(128, 4) X(128, 8) X(256, 4)
+// Two-sweep tiles (block = TX x (TY + ring rows) <= 1024 threads); each is
+// also a single-sweep tile (an odd sweep count starts with one single sweep
+// at the same shape).
+#define P19_SAT2_TILES(X) X(32, 4) X(32, 8) X(64, 4) X(64, 8) X(128, 4)
 
 bool p19_tile_ok(int v, Tile t) {
     if (v == V_PLAIN || is_point_form(v)) return plain_tile_ok(t);
@@ -497,7 +509,8 @@ hipError_t p19_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
     if (v == V_SAT2) {
 #define X(A, B)                                                                                           \
     if (t.tx == A && t.ty == B) {                                                                         \
-        hipLaunchKernelGGL((poisson19_sat2<A, B>), grid, dim3(A, B, 1), 0, s, src, dst, c, a.g, a.omega, t.tz, \
+        hipLaunchKernelGGL((poisson19_sat2<A, B>), grid, dim3(A, B + Sat2Shape<A, B>::EY, 1), 0, s, src, dst, c, a.g, \
+                           a.omega, t.tz,                                                                          \
                            a.remap, a.part);                                                              \
         return hipGetLastError();                                                                         \
     }
