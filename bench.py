@@ -130,7 +130,7 @@ def setup_workload(name, variant, dev, torch, synth, Plan, plan_kw=None):
             pts *= v
         meta = dict(workload=f"{name} Jacobi heat, interior {n}, FP64, {T} sweeps + residual", interior=list(n),
                     iterations=T, bytes_per_update=16, kernel_tag=f"{name}_{variant}", source="heat.hip",
-                    storage="f64")
+                    storage="f64", sweeps_per_launch=2 if variant == "saturated_t2" else 1)
         return plan, step, reset, pts * T, T, meta
     if name == "generic":
         w = synth.generic_box_workload()
@@ -171,8 +171,8 @@ def setup_workload(name, variant, dev, torch, synth, Plan, plan_kw=None):
         us = [synth.heat3d7_input(*n, stream=1 + b) for b, n in enumerate(sizes)]
         fs = [(torch.tensor(u, device=dev), torch.empty(u.shape, dtype=torch.float64, device=dev)) for u in us]
         pts = sum(n[0] * n[1] * n[2] for n in sizes)
-        if variant == "saturated":  # the batched graph, classes tuned
-            plan = BatchPlan(sizes, tune=TUNE)
+        if variant in ("saturated", "saturated_t2"):  # the batched graph, classes tuned
+            plan = BatchPlan(sizes, tune=TUNE, variant=variant)
 
             def step():
                 plan.run(fs, iterations=T)
@@ -210,7 +210,7 @@ def setup_workload(name, variant, dev, torch, synth, Plan, plan_kw=None):
         meta = dict(workload="64 independent heat3d7 FP64 grids, edges 32..160 (seeded), 50 sweeps each + "
                              "residuals; batched graph vs 64 separate plain runs",
                     interior=[len(sizes), pts], iterations=T, bytes_per_update=16, kernel_tag="heat3d7_batch",
-                    source="heat.hip", storage="f64")
+                    source="heat.hip", storage="f64", sweeps_per_launch=2 if variant == "saturated_t2" else 1)
         return plan, step, (lambda: None), pts * T, T, meta
     if name == "copy":
         # plain device-to-device copy of 1 GiB: the streaming ceiling, and the
@@ -463,7 +463,7 @@ def main():
         return bench_lhs(a, torch)
     forms = [a.variant]
     if a.variant == "best":
-        forms = ["saturated", "saturated_t2"] if a.workload == "poisson19" else ["saturated"]
+        forms = ["saturated", "saturated_t2"] if a.workload in ("poisson19", "heat3d7", "batch") else ["saturated"]
     sat = {v: time_variant(a.workload, v, a.steps, a.warmup, dev, torch, synth, Plan) for v in forms}
     variant = max(forms, key=lambda v: sat[v]["pts"] / sat[v]["wall"])
     main_r = sat[variant]

@@ -190,8 +190,9 @@ stencil_status validate_desc(const stencil_desc *d, Geom &g, int &rz) {
         return fail(STENCIL_E_INVAL, "unknown variant %d", d->variant);
     if (is_point_form(d->variant) && k != STENCIL_WAVE25 && k != STENCIL_POISSON19)
         return fail(STENCIL_E_UNSUPPORTED, "the per-point ablation forms are offered for WAVE25 and POISSON19");
-    if (d->variant == STENCIL_SATURATED_T2 && (k != STENCIL_POISSON19 || d->bc != STENCIL_BC_DIRICHLET))
-        return fail(STENCIL_E_UNSUPPORTED, "the two-sweep saturated form is offered for POISSON19 (Dirichlet)");
+    if (d->variant == STENCIL_SATURATED_T2 &&
+        ((k != STENCIL_POISSON19 && k != STENCIL_HEAT3D7) || d->bc != STENCIL_BC_DIRICHLET))
+        return fail(STENCIL_E_UNSUPPORTED, "the two-sweep saturated form is offered for POISSON19 and HEAT3D7 (Dirichlet)");
     if (d->tune < STENCIL_TUNE_FIXED || d->tune > STENCIL_TUNE_MODEL)
         return fail(STENCIL_E_INVAL, "unknown tune mode %d", d->tune);
     if (d->bc != STENCIL_BC_DIRICHLET && d->bc != STENCIL_BC_PERIODIC)

@@ -70,22 +70,29 @@ stencil_status capture(stencil_plan_s *p, void *const *fields, int T, hipStream_
         if ((e = launch_halo_copy(fields[2 * i], fields[2 * i + 1], 8, b->probs[i].g, 1, cap)) != hipSuccess)
             return abort_capture(e, "halo copy");
     const int nc = (int)b->classes.size();
+    std::vector<int> launches(nc, 0);  // per class; each launch flips the problems' buffers
     if ((e = hipEventRecord(b->evs[0], cap)) != hipSuccess) return abort_capture(e, "fork");
     for (int c = 0; c < nc; ++c) {
         const BatchClass &C = b->classes[c];
         hipStream_t s = b->side[c];
         if ((e = hipStreamWaitEvent(s, b->evs[0], 0)) != hipSuccess) return abort_capture(e, "fork wait");
-        for (int t = 0; t < T; ++t) {
-            double *part = (t == T - 1) ? b->d_part + C.item_base : nullptr;
-            if ((e = p->ops->batch_launch(C.variant, C.tile, b->d_probs, b->d_items + C.item_base, C.n_items, t & 1,
+        // a two-sweep class starts an odd sweep count with one single sweep
+        const int per = sweeps_per_launch(C.variant);
+        for (int t = 0; t < T;) {
+            const int v = (t == 0 && (T % per)) ? V_SATURATED : C.variant;
+            const int adv = sweeps_per_launch(v);
+            double *part = (t + adv == T) ? b->d_part + C.item_base : nullptr;
+            if ((e = p->ops->batch_launch(v, C.tile, b->d_probs, b->d_items + C.item_base, C.n_items, launches[c] & 1,
                                           C.grid, part, s)) != hipSuccess)
                 return abort_capture(e, "batch sweep");
+            t += adv;
+            ++launches[c];
         }
         if ((e = hipEventRecord(b->evs[1 + c], s)) != hipSuccess) return abort_capture(e, "join");
         if ((e = hipStreamWaitEvent(cap, b->evs[1 + c], 0)) != hipSuccess) return abort_capture(e, "join wait");
     }
-    if (T & 1)
-        for (int i = 0; i < b->count; ++i)
+    for (int i = 0; i < b->count; ++i)
+        if (launches[b->prob_class[i]] & 1)
             if ((e = launch_interior_copy(fields[2 * i + 1], fields[2 * i], 8, b->probs[i].g, 1, cap)) != hipSuccess)
                 return abort_capture(e, "tail copy");
     if ((e = hipStreamEndCapture(cap, &b->graph)) != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -192,6 +199,7 @@ extern "C" stencil_status stencil_plan_batch(const stencil_desc *ds, int32_t cou
     p->batch = b;
     b->count = count;
     b->probs.resize(count);
+    b->prob_class.assign(count, 0);
     // classes and their forms: tuned (or default) on the class's largest problem
     std::vector<int> cls(count);
     int ncls = 0;
@@ -227,6 +235,7 @@ extern "C" stencil_status stencil_plan_batch(const stencil_desc *ds, int32_t cou
         C.item_base = (int)items.size();
         for (int i = 0; i < count; ++i) {
             if (cls[i] != c) continue;
+            b->prob_class[i] = (int)b->classes.size();
             const Geom &g = geoms[i];
             seg[i] = (int)items.size();
             const int gx = (int)cdiv(g.nx, C.tile.tx), gy = (int)cdiv(g.ny, C.tile.ty), gz = (int)cdiv(g.nz, C.tile.tz);

@@ -150,6 +150,125 @@ __global__ __launch_bounds__(TX *TY) void heat3d7_sat(const double *__restrict__
     }
 }
 
+// Two sweeps per pass (SATURATED_T2): the block's TY rows of tile threads
+// compute sweep 1 and sweep 2 of their own column; EY extra rows of ring
+// threads compute sweep 1 on the one-cell ring around the tile (recomputed
+// by every block that needs it).  p^t planes sit in a four-plane LDS ring
+// with a two-cell halo, sweep-1 planes in a four-plane ring; sweep 2 runs two
+// planes behind sweep 1, one barrier per plane.  Each value is computed with
+// the same operations as heat3d7_sat_tile (z neighbours come from the LDS
+// ring instead of the register queue: the same numbers), so two sweeps equal
+// two launches of the single-sweep form bit for bit.  Dirichlet only.
+template <int TX, int TY>
+struct H3Sat2Shape {
+    static constexpr int W0 = TX + 4, PL0 = (TY + 4) * W0, W1 = TX + 2, PL1 = (TY + 2) * W1;
+    static constexpr int RS = 2 * W1 + 2 * TY;
+    static constexpr int EY0 = (RS + TX - 1) / TX;
+    static constexpr int EY = (TX * (TY + EY0)) % 64 == 0 ? EY0 : EY0 + 1;
+    static constexpr int NT = TX * (TY + EY);
+};
+
+template <int TX, int TY>
+__device__ __forceinline__ double heat3d7_sat2_tile(const double *__restrict__ src, double *__restrict__ dst,
+                                                    const Geom &g, double cc, double cn, int zb, int bx, int by,
+                                                    int bz, double (*r0)[H3Sat2Shape<TX, TY>::PL0],
+                                                    double (*r1)[H3Sat2Shape<TX, TY>::PL1]) {
+    using S = H3Sat2Shape<TX, TY>;
+    constexpr int W0 = S::W0, W1 = S::W1, NT = S::NT, RS = S::RS;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+    const int PX = g.nx + 2, PY = g.ny + 2;
+    const int k0 = bz * zb, k1 = min(k0 + zb, g.nz);
+    const bool tile_t = ty < TY;
+    const int xo = bx * TX + tx + 1, yo = by * TY + ty + 1;  // padded
+    const bool in_o = tile_t && xo <= g.nx && yo <= g.ny;
+    const bool ld_o = tile_t && xo < PX && yo < PY;
+    const long long col_o = (long long)yo * g.py + xo;
+    const int e0_o = (ty + 2) * W0 + tx + 2, e1_o = (ty + 1) * W1 + tx + 1;
+    const int q = tid - TX * TY;
+    const bool has_r = !tile_t && q < RS;
+    int ex = 0, ey = 0;
+    if (q < W1) {
+        ex = q;
+    } else if (q < 2 * W1) {
+        ex = q - W1;
+        ey = TY + 1;
+    } else if (q < 2 * W1 + TY) {
+        ey = q - 2 * W1 + 1;
+    } else {
+        ex = W1 - 1;
+        ey = q - 2 * W1 - TY + 1;
+    }
+    const int xr = bx * TX + ex, yr = by * TY + ey;
+    const bool in_r = has_r && xr >= 1 && xr <= g.nx && yr >= 1 && yr <= g.ny;
+    const bool in_a = tile_t ? in_o : in_r, has_a = tile_t || has_r;
+    const int e0_a = tile_t ? e0_o : (ey + 1) * W0 + ex + 1, e1_a = tile_t ? e1_o : ey * W1 + ex;
+
+    HaloStager<double, TX, TY, 2, true, NT> halo;
+    halo.init(tid, bx * TX + 1, by * TY + 1, g.py, PX, PY);
+    const int zlo = k0, zhi = k1 + 1;
+    for (int z = zlo - 1; z <= zlo; ++z) {
+        if (z < 0) continue;
+        const double *pl = src + (long long)z * g.pz;
+        if (tile_t) r0[z & 3][e0_o] = ld_o ? pl[col_o] : 0.0;
+        halo.load(pl);
+        halo.store(r0[z & 3]);
+    }
+    double ctr = ld_o ? src[col_o + (long long)(zlo + 1) * g.pz] : 0.0;
+    halo.load(src + (long long)(zlo + 1) * g.pz);
+    double acc = 0.0;
+    for (int zA = zlo; zA <= zhi + 1; ++zA) {
+        if (zA <= zhi) {
+            if (tile_t) r0[(zA + 1) & 3][e0_o] = ctr;
+            halo.store(r0[(zA + 1) & 3]);
+            if (zA < zhi && zA + 2 <= g.nz + 1) {
+                const double *pl = src + (long long)(zA + 2) * g.pz;
+                ctr = ld_o ? pl[col_o] : 0.0;
+                halo.load(pl);
+            }
+        }
+        __syncthreads();
+        if (zA <= zhi && has_a) {  // sweep 1 at plane zA
+            const double *m = r0[(zA - 1) & 3], *o = r0[zA & 3], *u = r0[(zA + 1) & 3];
+            const int e = e0_a;
+            double v = o[e];
+            if (zA >= 1 && zA <= g.nz && in_a) {
+                const double s = ((o[e - 1] + o[e + 1]) + (o[e - W0] + o[e + W0])) + (m[e] + u[e]);
+                v = fma(cn, s, cc * o[e]);
+            }
+            r1[zA & 3][e1_a] = v;
+        }
+        const int zc = zA - 2;  // sweep 2 at plane zc
+        if (zc >= k0 + 1 && in_o) {
+            const double *m = r1[(zc - 1) & 3], *o = r1[zc & 3], *u = r1[(zc + 1) & 3];
+            const int e = e1_o;
+            const double s = ((o[e - 1] + o[e + 1]) + (o[e - W1] + o[e + W1])) + (m[e] + u[e]);
+            const double v = fma(cn, s, cc * o[e]);
+            dst[col_o + (long long)zc * g.pz] = v;
+            const double d = v - o[e];
+            acc = fma(d, d, acc);
+        }
+    }
+    return acc;
+}
+
+template <int TX, int TY>
+__global__ __launch_bounds__((H3Sat2Shape<TX, TY>::NT)) void heat3d7_sat2(const double *__restrict__ src,
+                                                                           double *__restrict__ dst, Geom g,
+                                                                           double cc, double cn, int zb, int remap,
+                                                                           double *__restrict__ part) {
+    using S = H3Sat2Shape<TX, TY>;
+    __shared__ double r0[4][S::PL0];
+    __shared__ double r1[4][S::PL1];
+    __shared__ double red[kMaxWaves];
+    int bx, by, bz;
+    tile_coords(remap, bx, by, bz);
+    const double acc = heat3d7_sat2_tile<TX, TY>(src, dst, g, cc, cn, zb, bx, by, bz, r0, r1);
+    if (part) {
+        const double s = block_sum_f64(acc, red);
+        if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = s;
+    }
+}
+
 // Persistent work-list forms: each block walks items blockIdx.x, +gridDim.x,
 // ... and runs the same tile body as the single-problem kernel, so a batched
 // problem is bit-identical to its own run with the same form and shape.
@@ -164,6 +283,28 @@ __global__ __launch_bounds__(TX *TY) void heat3d7_sat_batch(const BatchProb *__r
         const BatchProb &P = probs[w.prob];
         const double acc = heat3d7_sat_tile<TX, TY>(P.f[parity], P.f[parity ^ 1], P.g, P.cc, P.cn, zb, w.bx, w.by,
                                                     w.bz, tile);
+        if (part) {
+            const double s = block_sum_f64(acc, red);
+            if (threadIdx.x == 0 && threadIdx.y == 0) part[it] = s;
+        }
+        __syncthreads();  // LDS is reused by the next item
+    }
+}
+
+template <int TX, int TY>
+__global__ __launch_bounds__((H3Sat2Shape<TX, TY>::NT)) void heat3d7_sat2_batch(const BatchProb *__restrict__ probs,
+                                                                                 const BatchItem *__restrict__ items,
+                                                                                 int n_items, int parity, int zb,
+                                                                                 double *__restrict__ part) {
+    using S = H3Sat2Shape<TX, TY>;
+    __shared__ double r0[4][S::PL0];
+    __shared__ double r1[4][S::PL1];
+    __shared__ double red[kMaxWaves];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const BatchItem w = items[it];
+        const BatchProb &P = probs[w.prob];
+        const double acc = heat3d7_sat2_tile<TX, TY>(P.f[parity], P.f[parity ^ 1], P.g, P.cc, P.cn, zb, w.bx, w.by,
+                                                     w.bz, r0, r1);
         if (part) {
             const double s = block_sum_f64(acc, red);
             if (threadIdx.x == 0 && threadIdx.y == 0) part[it] = s;
@@ -209,9 +350,19 @@ hipError_t h2_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 #define HEAT3D7_SAT_TILES(X) X(32, 2) X(32, 4) X(32, 8) X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(128, 1) X(128, 2) \
     X(128, 4) X(256, 1) X(256, 2)
 
+// Two-sweep tiles (block = TX x (TY + ring rows) <= 1024 threads); each is
+// also a single-sweep tile (an odd sweep count starts with one single sweep).
+#define HEAT3D7_SAT2_TILES(X) X(32, 4) X(32, 8) X(64, 4) X(64, 8) X(128, 4)
+
 bool h3_tile_ok(int v, Tile t) {
     if (v == V_PLAIN) return plain_tile_ok(t);
     if (t.tz < 1) return false;
+    if (v == V_SAT2) {
+#define X(a, b) if (t.tx == a && t.ty == b) return true;
+        HEAT3D7_SAT2_TILES(X)
+#undef X
+        return false;
+    }
 #define X(a, b) if (t.tx == a && t.ty == b) return true;
     HEAT3D7_SAT_TILES(X)
 #undef X
@@ -222,6 +373,14 @@ int h3_sat_tiles(Tile *out, int max) {
     int n = 0;
 #define X(a, b) if (n < max) out[n++] = Tile{a, b, 0};
     HEAT3D7_SAT_TILES(X)
+#undef X
+    return n;
+}
+
+int h3_sat2_tiles(Tile *out, int max) {
+    int n = 0;
+#define X(a, b) if (n < max) out[n++] = Tile{a, b, 0};
+    HEAT3D7_SAT2_TILES(X)
 #undef X
     return n;
 }
@@ -238,6 +397,17 @@ hipError_t h3_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(heat3d7_plain, grid, dim3(t.tx, t.ty, t.tz), 0, s, src, dst, a.g, a.c[0], a.c[1],
                            a.part);
         return hipGetLastError();
+    }
+    if (v == V_SAT2) {
+#define X(A, B)                                                                                              \
+    if (t.tx == A && t.ty == B) {                                                                            \
+        hipLaunchKernelGGL((heat3d7_sat2<A, B>), grid, dim3(A, B + H3Sat2Shape<A, B>::EY, 1), 0, s, src, dst, a.g, \
+                           a.c[0], a.c[1], t.tz, a.remap, a.part);                                            \
+        return hipGetLastError();                                                                            \
+    }
+        HEAT3D7_SAT2_TILES(X)
+#undef X
+        return hipErrorInvalidValue;
     }
 #define X(A, B)                                                                                        \
     if (t.tx == A && t.ty == B) {                                                                      \
@@ -257,6 +427,17 @@ hipError_t h3_batch_launch(int v, Tile t, const BatchProb *probs, const BatchIte
                            part);
         return hipGetLastError();
     }
+    if (v == V_SAT2) {
+#define X(A, B)                                                                                                 \
+    if (t.tx == A && t.ty == B) {                                                                               \
+        hipLaunchKernelGGL((heat3d7_sat2_batch<A, B>), dim3(grid), dim3(A, B + H3Sat2Shape<A, B>::EY, 1), 0, s, probs, \
+                           items, n_items, parity, t.tz, part);                                                  \
+        return hipGetLastError();                                                                               \
+    }
+        HEAT3D7_SAT2_TILES(X)
+#undef X
+        return hipErrorInvalidValue;
+    }
 #define X(A, B)                                                                                                \
     if (t.tx == A && t.ty == B) {                                                                              \
         hipLaunchKernelGGL((heat3d7_sat_batch<A, B>), dim3(grid), dim3(A, B, 1), 0, s, probs, items, n_items,   \
@@ -271,6 +452,6 @@ hipError_t h3_batch_launch(int v, Tile t, const BatchProb *probs, const BatchIte
 }  // namespace
 
 KindOps heat2d5_ops = {h2_tile_ok, nullptr, nullptr, h2_nblocks, h2_launch, nullptr};
-KindOps heat3d7_ops = {h3_tile_ok, h3_sat_tiles, nullptr, h3_nblocks, h3_launch, h3_batch_launch};
+KindOps heat3d7_ops = {h3_tile_ok, h3_sat_tiles, h3_sat2_tiles, h3_nblocks, h3_launch, h3_batch_launch};
 
 }  // namespace stn

@@ -20,6 +20,7 @@ struct BatchState {
     int count = 0, n_items = 0;
     std::vector<stn::BatchProb> probs;  // host copy of the problem table
     std::vector<BatchClass> classes;
+    std::vector<int> prob_class;        // index into classes, per problem
     stn::BatchItem *d_items = nullptr;  // class-major, then problem, then tile (x fastest)
     stn::BatchProb *d_probs = nullptr;
     int *d_seg = nullptr;               // per problem: item begin [count], item end [count]
@@ -37,7 +38,7 @@ struct BatchState {
 
 struct stencil_plan_s {
     int kind = 0, dtype = 0, bc = 0;
-    int variant = 0;            // resolved: stn::V_PLAIN or stn::V_SATURATED
+    int variant = 0;            // resolved form (stn::Variant)
     stn::Tile tile{};           // resolved launch shape
     stn::Geom g{};
     int rz = 0;                 // z halo width (0 for 2-D)

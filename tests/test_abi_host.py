@@ -54,7 +54,10 @@ BAD = [
     (dict(kind="generic", n=(10, 10, 10), coef=(1.0,), taps=[(5, 0, 0)], cids=[0], radius=4), S.E_INVAL, "radius"),
     (dict(kind="generic", n=(10, 10, 10), coef=(1.0,), taps=[(1, 0, 0)], cids=[3], radius=1), S.E_INVAL, "id"),
     (dict(kind="wave25", n=(10, 10, 10), coef=(1, 2, 3, 4, 5), variant="saturated_t2"), S.E_UNSUPPORTED, "two-sweep"),
-    (dict(kind="heat3d7", n=(10, 10, 10), coef=(0.4, 0.1), variant="saturated_t2"), S.E_UNSUPPORTED, "two-sweep"),
+    (dict(kind="heat3d7", n=(10, 10, 10), coef=(0.4, 0.1), variant="saturated_t2", bc="periodic"), S.E_UNSUPPORTED,
+     "two-sweep"),
+    (dict(kind="generic", n=(10, 10, 10), coef=(1.0,), taps=[(1, 0, 0)], cids=[0], radius=1, variant="saturated_t2"),
+     S.E_UNSUPPORTED, "two-sweep"),
 ]
 
 

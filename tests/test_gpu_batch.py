@@ -44,7 +44,8 @@ def single(n, u0, T, dev, **kw):
 
 
 @pytest.mark.parametrize("variant,tile", [("saturated", (32, 8, 8)), ("saturated", (64, 4, 16)),
-                                          ("plain", (64, 4, 1)), ("plain", (128, 2, 1))])
+                                          ("plain", (64, 4, 1)), ("plain", (128, 2, 1)),
+                                          ("saturated_t2", (32, 8, 8)), ("saturated_t2", (64, 4, 16))])
 @pytest.mark.parametrize("T", [3, 4])
 def test_batch_bitwise_equals_single(dev, variant, tile, T):
     from paper_2306_13002_amd.stencil import BatchPlan
@@ -119,3 +120,20 @@ def test_batch_tuned_workload(dev):
     for i in sorted(range(len(sizes)), key=lambda b: np.prod(sizes[b]))[:2]:
         want, _ = oracle.heat(us[i], 50, 0.4, 0.1)
         assert maxrel(inner(fs[i][0].cpu().numpy(), 1), inner(want, 1)) <= 1e-12
+
+
+def test_batch_two_sweep_equals_single_sweep_batch(dev):
+    """A batch whose classes run two sweeps per launch gives the single-sweep
+    batch's result bit for bit (odd T: one single sweep first)."""
+    from paper_2306_13002_amd.stencil import BatchPlan
+    for T in (5, 6):
+        out = []
+        for variant in ("saturated", "saturated_t2"):
+            us, fs = fields_for(SIZES, dev)
+            bp = BatchPlan(SIZES, variant=variant, tile=(64, 4, 16))
+            bp.run(fs, iterations=T)
+            out.append(([f[0].cpu().numpy() for f in fs], bp.residuals()))
+            bp.close()
+        for a, b in zip(out[0][0], out[1][0]):
+            assert np.array_equal(a, b)
+        assert list(out[0][1]) == list(out[1][1])

@@ -107,6 +107,32 @@ def test_heat3d7_saturated(dev, tile, zb):
     assert abs(gr - wr) <= 1e-10 * wr
 
 
+H3_SAT2_TILES = [(32, 4), (32, 8), (64, 4), (64, 8), (128, 4)]
+
+
+@pytest.mark.parametrize("tile", H3_SAT2_TILES)
+@pytest.mark.parametrize("zb", [1, 5, 64])
+@pytest.mark.parametrize("remap", ["natural", "xcd"])
+def test_heat3d7_two_sweep_equals_saturated_bitwise(dev, tile, zb, remap):
+    u0 = synth.heat3d7_input(*N3, stream=6)
+    for T in (1, 2, 3, 4, 5):
+        ref, gr = run_jacobi("heat3d7", u0, N3, dev, T, coef=(0.4, 0.1), variant="saturated",
+                             tile=(tile[0], tile[1], zb), tile_map=remap)
+        got, gg = run_jacobi("heat3d7", u0, N3, dev, T, coef=(0.4, 0.1), variant="saturated_t2",
+                             tile=(tile[0], tile[1], zb), tile_map=remap)
+        assert np.array_equal(got, ref), T
+        assert gg == gr, T
+
+
+def test_heat3d7_two_sweep_vs_oracle(dev):
+    u0 = synth.heat3d7_input(*N3, stream=7)
+    want, wr = oracle.heat(u0, 6, 0.4, 0.1)
+    got, gr = run_jacobi("heat3d7", u0, N3, dev, 6, coef=(0.4, 0.1), variant="saturated_t2", tile=(64, 4, 8))
+    assert maxrel(inner(got, 1), inner(want, 1)) <= 1e-12
+    assert np.array_equal(got[0], u0[0]) and np.array_equal(got[:, :, -1], u0[:, :, -1])
+    assert abs(gr - wr) <= 1e-10 * wr
+
+
 @pytest.mark.parametrize("variant", ["plain", "saturated"])
 def test_heat3d7_periodic(dev, variant):
     u0 = synth.heat3d7_input(33, 20, 17, stream=5)
