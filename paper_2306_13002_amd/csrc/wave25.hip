@@ -18,9 +18,10 @@
 // u_next = fma(vsq, L, 2u - u_prev).  Loads: a block owns a TX x TY column
 // tile (BY thread rows, RY rows per thread) and streams z; each column keeps
 // the nine planes z-4..z+4 in a register queue (one global load per point),
-// the in-plane +-4 neighbours come from an LDS tile with a 4-cell ring, and
-// every load of the next plane (queue head, ring, u_prev, vsq) is issued
-// before the current plane is computed ("bulk load").
+// the in-plane +-4 neighbours come from an LDS tile with a 4-cell ring (the
+// ring loaded four planes ahead, together with the queue heads, and held in
+// registers), and every load for the next plane (queue head, ring, u_prev,
+// vsq) is issued before the current plane is computed ("bulk load").
 #include "internal.hpp"
 
 namespace stn {
@@ -216,7 +217,18 @@ __global__ __launch_bounds__(TX *BY) void wave25_sat(const double *__restrict__ 
         up[m] = in[m] ? pn[o] : 0.0;
         vv[m] = in[m] ? vsq[o] : 0.0;
     }
-    halo.load(cur + (long long)(k0 + R) * g.pz);
+    // The ring cells of plane zc are loaded with the queue heads of plane
+    // zc (four planes before the plane is computed), when the neighbouring
+    // blocks load the same cells as their own queue heads, so the ring is
+    // mostly served from L2; hq[s] holds the ring of plane zc + s.
+    constexpr int HR = decltype(halo)::HR;
+    double hq[R + 1][HR];
+#pragma unroll
+    for (int s = 0; s <= R; ++s) {
+        halo.load(cur + (long long)(k0 + R + s) * g.pz);
+#pragma unroll
+        for (int h = 0; h < HR; ++h) hq[s][h] = halo.val[h];
+    }
     double acc = 0.0;
 
     for (int k = k0; k < k1; ++k) {
@@ -224,6 +236,8 @@ __global__ __launch_bounds__(TX *BY) void wave25_sat(const double *__restrict__ 
         double *t = tile[b];
 #pragma unroll
         for (int m = 0; m < RY; ++m) t[me[m]] = q[m][4];
+#pragma unroll
+        for (int h = 0; h < HR; ++h) halo.val[h] = hq[0][h];
         halo.store(t);
         double upc[RY], vvc[RY], qn[RY];
 #pragma unroll
@@ -235,7 +249,15 @@ __global__ __launch_bounds__(TX *BY) void wave25_sat(const double *__restrict__ 
         if (k + 1 < k1) {  // bulk load of plane zc+1 (queue head zc+5)
 #pragma unroll
             for (int m = 0; m < RY; ++m) qn[m] = (ld[m] && zc + 5 < PZ) ? cur[col[m] + (long long)(zc + 5) * g.pz] : 0.0;
-            halo.load(cur + (long long)(zc + 1) * g.pz);
+#pragma unroll
+            for (int s = 0; s < R; ++s)
+#pragma unroll
+                for (int h = 0; h < HR; ++h) hq[s][h] = hq[s + 1][h];
+            if (k + R + 1 < k1) {  // the ring of plane zc+5, computed at iteration k+5
+                halo.load(cur + (long long)(zc + R + 1) * g.pz);
+#pragma unroll
+                for (int h = 0; h < HR; ++h) hq[R][h] = halo.val[h];
+            }
 #pragma unroll
             for (int m = 0; m < RY; ++m) {
                 const long long o = col[m] + (long long)(zc + 1) * g.pz;
