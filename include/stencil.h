@@ -102,13 +102,13 @@ typedef enum { STENCIL_F32 = 1, STENCIL_F64 = 2 } stencil_dtype; /* storage type
  *                 the z-streaming register queue and LDS tile).
  * They use the plain launch shapes and are never picked by the tuners.
  *
- * SATURATED_T2 (POISSON19, Dirichlet): the saturated form with two sweeps per
- * pass over memory -- the first sweep is recomputed on a one-cell ring around
- * each tile so the second can follow it plane by plane, and the coefficient
- * streams are read once per two sweeps.  Bit-identical to SATURATED at the
- * same tile, z-block and tile map (an odd sweep count starts with one
- * SATURATED sweep).  Tuned exhaustively (AUTO and the cost model do not
- * consider it). */
+ * SATURATED_T2 (POISSON19 and HEAT3D7, Dirichlet; single and batched plans):
+ * the saturated form with two sweeps per pass over memory -- the first sweep
+ * is recomputed on a one-cell ring around each tile so the second can follow
+ * it plane by plane, and every input stream is read once per two sweeps.
+ * Bit-identical to SATURATED at the same tile, z-block and tile map (an odd
+ * sweep count starts with one SATURATED sweep).  Tuned exhaustively (AUTO and
+ * the cost model do not consider it). */
 typedef enum {
     STENCIL_PLAIN = 0,
     STENCIL_SATURATED = 1,

@@ -9,7 +9,7 @@ namespace stn {
 
 // Forms.  V_CSE_SAT, V_CSE_BULK and V_ACCSAT_POINT are the per-point forms of
 // the paper's ablation (rewritten arithmetic only, bulk load only, both);
-// V_SAT2 is the saturated form with two sweeps per pass (POISSON19).
+// V_SAT2 is the saturated form with two sweeps per pass (POISSON19, HEAT3D7).
 enum Variant { V_PLAIN = 0, V_SATURATED = 1, V_CSE_SAT = 3, V_CSE_BULK = 4, V_ACCSAT_POINT = 5, V_SAT2 = 6 };
 inline bool is_point_form(int v) { return v == V_CSE_SAT || v == V_CSE_BULK || v == V_ACCSAT_POINT; }
 // Sweeps one launch performs.
