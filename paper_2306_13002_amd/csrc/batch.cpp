@@ -2,8 +2,8 @@
 //
 // Problems are grouped into size classes by their largest interior edge
 // (<= 64, then buckets of 32).  Each class gets one form and launch shape
-// (from the autotuner on the class's largest problem, or the defaults) and a
-// work list of (problem, tile) items.  A run is one hipGraph: the halo copies,
+// (tuned by timing the class's own work list over all its problems, or the
+// defaults) and a work list of (problem, tile) items.  A run is one hipGraph: the halo copies,
 // then per class a chain of T persistent work-list launches (classes are
 // parallel branches of the graph), then the odd-T tail copies.  The graph is
 // captured at the first run with a given (T, field pointers) and replayed
@@ -12,13 +12,17 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/stencil.h"
 #include "internal.hpp"
 #include "plan.hpp"
+#include "tune.hpp"
 
 namespace stn {
 
@@ -30,9 +34,178 @@ void free_plan(stencil_plan_s *p);
 
 namespace {
 
+constexpr int kBatchGrid = 2048;  // blocks of a work-list launch (at most)
+
 int size_class(const Geom &g) {
     const int m = std::max(g.nx, std::max(g.ny, g.nz));
     return m <= 64 ? 0 : (m - 65) / 32 + 1;
+}
+
+// The work list of one class at launch shape t: items of the class's
+// problems in spatial order (problem, z, y, x), each with its residual slot,
+// then arranged for the XCDs.  Block j of a launch runs on XCD j mod 8 and
+// visits items j, j + grid, ... (grid a multiple of 8 when there are enough
+// items): list position q goes to XCD q mod 8, so the spatial order is cut
+// into eight contiguous chunks, chunk x filling positions x, x + 8, ...
+// Tiles that share halo cells then run on one XCD at about the same time and
+// the shared cells come from its L2.  seg (optional) receives each problem's
+// [begin, end) slot range relative to the class.
+std::vector<BatchItem> class_items(const std::vector<int> &members, const std::vector<Geom> &geoms, Tile t,
+                                   std::vector<std::pair<int, int>> *seg) {
+    std::vector<BatchItem> ci;
+    for (int i : members) {
+        const Geom &g = geoms[i];
+        const int b0 = (int)ci.size();
+        const int gx = (int)cdiv(g.nx, t.tx), gy = (int)cdiv(g.ny, t.ty), gz = (int)cdiv(g.nz, t.tz);
+        for (int z = 0; z < gz; ++z)
+            for (int y = 0; y < gy; ++y)
+                for (int x = 0; x < gx; ++x) ci.push_back({i, x, y, z, (int)ci.size()});
+        if (seg) seg->push_back({b0, (int)ci.size()});
+    }
+    const int n = (int)ci.size();
+    if (n >= kBatchGrid) {
+        const int chunk = (int)cdiv(n, 8);
+        std::vector<BatchItem> perm;
+        perm.reserve(n);
+        for (int q = 0; q < 8 * chunk; ++q) {
+            const int sidx = (q & 7) * chunk + (q >> 3);
+            if (sidx < n) perm.push_back(ci[sidx]);
+        }
+        ci.swap(perm);
+    }
+    return ci;
+}
+
+// Tune one size class where it runs: every candidate form and shape is timed
+// as the class's work-list kernel over all of the class's problems, on
+// scratch grids of their extents.  The class's working set is the sum of its
+// problems' and mostly leaves the Infinity Cache, which the largest problem
+// timed alone does not show (its best shape can lose by 25 % in the batch).
+stencil_status tune_class(const std::vector<int> &members, const std::vector<Geom> &geoms, double cc, double cn,
+                          const TuneRequest &rq, TuneEntry *best) {
+    int big = members[0];
+    for (int i : members)
+        if ((long long)geoms[i].nx * geoms[i].ny * geoms[i].nz >
+            (long long)geoms[big].nx * geoms[big].ny * geoms[big].nz)
+            big = i;
+    TuneRequest r = rq;
+    r.tile_map = 1;  // work lists fix the block order themselves
+    const std::vector<Cand> cands = tune_candidates(&heat3d7_ops, STENCIL_HEAT3D7, geoms[big], r);
+    if (cands.empty()) return fail(STENCIL_E_UNSUPPORTED, "no launch shape matches the requested tile fields");
+    const int m = (int)members.size();
+    struct Scratch {
+        std::vector<void *> ptrs;
+        hipStream_t s = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Scratch() {
+            for (void *q : ptrs)
+                if (q) (void)hipFree(q);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } sc;
+    hipError_t e;
+    if ((e = hipStreamCreate(&sc.s)) != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    if ((e = hipEventCreate(&sc.e0)) != hipSuccess || (e = hipEventCreate(&sc.e1)) != hipSuccess)
+        return hip_fail(e, "hipEventCreate");
+    std::vector<BatchProb> probs(m);
+    std::vector<Geom> tg(geoms);  // dense copies of the members' layouts
+    for (int k = 0; k < m; ++k) {
+        Geom g = geoms[members[k]];
+        g.py = g.nx + 2;
+        g.pz = (long long)(g.nx + 2) * (g.ny + 2);
+        tg[members[k]] = g;
+        const long long n = g.pz * (g.nz + 2);
+        for (int f = 0; f < 2; ++f) {
+            void *q = nullptr;
+            if ((e = hipMalloc(&q, sizeof(double) * (size_t)n)) != hipSuccess)
+                return fail(STENCIL_E_NOMEM, "class tuning buffers: %s", hipGetErrorString(e));
+            sc.ptrs.push_back(q);
+            if ((e = launch_fill(q, n, 8, 1.0, sc.s)) != hipSuccess) return hip_fail(e, "fill");
+            probs[k].f[f] = (double *)q;
+        }
+        probs[k].g = g;
+        probs[k].cc = cc;
+        probs[k].cn = cn;
+    }
+    // items refer to problems by their index in `probs`
+    std::vector<int> local(m);
+    std::vector<Geom> lg(m);
+    for (int k = 0; k < m; ++k) {
+        local[k] = k;
+        lg[k] = tg[members[k]];
+    }
+    size_t max_items = 0;
+    for (const Cand &c : cands) {
+        long long n = 0;
+        for (const Geom &g : lg) n += cdiv(g.nx, c.tile.tx) * cdiv(g.ny, c.tile.ty) * cdiv(g.nz, c.tile.tz);
+        max_items = std::max(max_items, (size_t)n);
+    }
+    void *d_probs = nullptr, *d_items = nullptr;
+    if ((e = hipMalloc(&d_probs, sizeof(BatchProb) * m)) != hipSuccess) return fail(STENCIL_E_NOMEM, "class tuning");
+    sc.ptrs.push_back(d_probs);
+    if ((e = hipMalloc(&d_items, sizeof(BatchItem) * max_items)) != hipSuccess)
+        return fail(STENCIL_E_NOMEM, "class tuning");
+    sc.ptrs.push_back(d_items);
+    if ((e = hipMemcpyAsync(d_probs, probs.data(), sizeof(BatchProb) * m, hipMemcpyHostToDevice, sc.s)) != hipSuccess)
+        return hip_fail(e, "problem table upload");
+    auto time_cand = [&](const Cand &c, int T, int reps, double *us) -> hipError_t {
+        const std::vector<BatchItem> items = class_items(local, lg, c.tile, nullptr);
+        hipError_t err = hipMemcpyAsync(d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice,
+                                        sc.s);
+        if (err != hipSuccess) return err;
+        const int n = (int)items.size(), grid = std::min(n, kBatchGrid);
+        std::vector<double> ts;
+        for (int rp = 0; rp < reps + 1; ++rp) {  // the first repetition warms up
+            if ((err = hipEventRecord(sc.e0, sc.s)) != hipSuccess) return err;
+            for (int t = 0; t < T; ++t)
+                if ((err = heat3d7_ops.batch_launch(c.variant, c.tile, (const BatchProb *)d_probs,
+                                                    (const BatchItem *)d_items, n, t & 1, grid, nullptr, sc.s)) !=
+                    hipSuccess)
+                    return err;
+            if ((err = hipEventRecord(sc.e1, sc.s)) != hipSuccess) return err;
+            if ((err = hipEventSynchronize(sc.e1)) != hipSuccess) return err;
+            float ms = 0;
+            if ((err = hipEventElapsedTime(&ms, sc.e0, sc.e1)) != hipSuccess) return err;
+            if (rp > 0) ts.push_back(1e3 * ms / (T * sweeps_per_launch(c.variant)));
+        }
+        std::sort(ts.begin(), ts.end());
+        *us = ts[ts.size() / 2];
+        return hipSuccess;
+    };
+    double probe = 0;
+    if ((e = time_cand(cands[0], 2, 1, &probe)) != hipSuccess) return hip_fail(e, "class tuning launch");
+    const int T = (int)std::min(50.0, std::max(2.0, 1000.0 / std::max(probe, 1.0)));
+    TuneEntry bv{};
+    bv.us = 1e300;
+    for (const Cand &c : cands) {
+        double us = 0;
+        if ((e = time_cand(c, T, 3, &us)) != hipSuccess) return hip_fail(e, "class tuning launch");
+        logf("tune batch class (%d problems) v=%d tile=(%d,%d,%d): %.2f us/sweep", m, c.variant, c.tile.tx, c.tile.ty,
+             c.tile.tz, us);
+        if (us < bv.us) {
+            bv.us = us;
+            bv.variant = c.variant;
+            bv.tile = c.tile;
+            bv.remap = 0;
+        }
+    }
+    if ((e = hipStreamSynchronize(sc.s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    *best = bv;
+    return STENCIL_OK;
+}
+
+// Cache key of a class: its problems' extents (in descriptor order) and the
+// request's fixed fields.
+std::string class_key(const std::vector<int> &members, const std::vector<Geom> &geoms, const TuneRequest &rq) {
+    unsigned h = 2166136261u;
+    for (int i : members)
+        for (int v : {geoms[i].nx, geoms[i].ny, geoms[i].nz}) h = (h ^ (unsigned)v) * 16777619u;
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "batch/k%d/m%d/h%08x/v%d/t%d,%d,%d", STENCIL_HEAT3D7, (int)members.size(), h,
+                  rq.variant, rq.tile_x, rq.tile_y, rq.zblock);
+    return buf;
 }
 
 void destroy_graph(BatchState *b) {
@@ -219,33 +392,49 @@ extern "C" stencil_status stencil_plan_batch(const stencil_desc *ds, int32_t cou
     stencil_status st = STENCIL_OK;
     for (int c = 0; c < ncls && st == STENCIL_OK; ++c) {
         if (rep[c] < 0) continue;
+        std::vector<int> members;
+        for (int i = 0; i < count; ++i)
+            if (cls[i] == c) members.push_back(i);
         stencil_desc d = ds[rep[c]];
         d.variant = ds[0].variant;
-        d.tune = ds[0].tune;
+        d.tune = STENCIL_TUNE_FIXED;  // validates the request and resolves the defaults
         d.tile_x = ds[0].tile_x;
         d.tile_y = ds[0].tile_y;
         d.zblock = ds[0].zblock;
         d.tile_map = 1;
-        stencil_plan_t rp = nullptr;
-        if ((st = stencil_plan(&d, &rp)) != STENCIL_OK) break;
         BatchClass C;
-        C.variant = rp->variant;
-        C.tile = rp->tile;
-        free_plan(rp);
-        C.item_base = (int)items.size();
-        for (int i = 0; i < count; ++i) {
-            if (cls[i] != c) continue;
-            b->prob_class[i] = (int)b->classes.size();
-            const Geom &g = geoms[i];
-            seg[i] = (int)items.size();
-            const int gx = (int)cdiv(g.nx, C.tile.tx), gy = (int)cdiv(g.ny, C.tile.ty), gz = (int)cdiv(g.nz, C.tile.tz);
-            for (int z = 0; z < gz; ++z)
-                for (int y = 0; y < gy; ++y)
-                    for (int x = 0; x < gx; ++x) items.push_back({i, x, y, z});
-            seg[count + i] = (int)items.size();
+        const bool open = !is_point_form(d.variant) &&
+                          (d.variant == STENCIL_AUTO || !d.tile_x || !d.tile_y || !d.zblock);
+        if (ds[0].tune != STENCIL_TUNE_FIXED && open) {  // EXHAUSTIVE and MODEL: timed in place
+            const TuneRequest rq{d.variant, d.tile_x, d.tile_y, d.zblock, 1};
+            const std::string key = class_key(members, geoms, rq);
+            TuneEntry te{};
+            if (!tune_lookup(key, &te)) {
+                if ((st = tune_class(members, geoms, ds[rep[c]].coef[0], ds[rep[c]].coef[1], rq, &te)) != STENCIL_OK)
+                    break;
+                tune_store(key, te);
+            }
+            C.variant = te.variant;
+            C.tile = te.tile;
+        } else {
+            stencil_plan_t rp = nullptr;
+            if ((st = stencil_plan(&d, &rp)) != STENCIL_OK) break;
+            C.variant = rp->variant;
+            C.tile = rp->tile;
+            free_plan(rp);
         }
-        C.n_items = (int)items.size() - C.item_base;
-        C.grid = std::min(C.n_items, 2048);
+        C.item_base = (int)items.size();
+        std::vector<std::pair<int, int>> ranges;
+        std::vector<BatchItem> ci = class_items(members, geoms, C.tile, &ranges);
+        for (size_t k = 0; k < members.size(); ++k) {
+            const int i = members[k];
+            b->prob_class[i] = (int)b->classes.size();
+            seg[i] = C.item_base + ranges[k].first;
+            seg[count + i] = C.item_base + ranges[k].second;
+        }
+        C.n_items = (int)ci.size();
+        C.grid = std::min(C.n_items, kBatchGrid);
+        items.insert(items.end(), ci.begin(), ci.end());
         logf("batch class %d: rep %d variant=%d tile=(%d,%d,%d) items=%d", c, rep[c], C.variant, C.tile.tx, C.tile.ty,
              C.tile.tz, C.n_items);
         b->classes.push_back(C);

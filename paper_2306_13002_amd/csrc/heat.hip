@@ -285,7 +285,7 @@ __global__ __launch_bounds__(TX *TY) void heat3d7_sat_batch(const BatchProb *__r
                                                     w.bz, tile);
         if (part) {
             const double s = block_sum_f64(acc, red);
-            if (threadIdx.x == 0 && threadIdx.y == 0) part[it] = s;
+            if (threadIdx.x == 0 && threadIdx.y == 0) part[w.slot] = s;
         }
         __syncthreads();  // LDS is reused by the next item
     }
@@ -307,7 +307,7 @@ __global__ __launch_bounds__((H3Sat2Shape<TX, TY>::NT)) void heat3d7_sat2_batch(
                                                      w.bz, r0, r1);
         if (part) {
             const double s = block_sum_f64(acc, red);
-            if (threadIdx.x == 0 && threadIdx.y == 0) part[it] = s;
+            if (threadIdx.x == 0 && threadIdx.y == 0) part[w.slot] = s;
         }
         __syncthreads();  // LDS is reused by the next item
     }
@@ -322,7 +322,7 @@ __global__ void heat3d7_plain_batch(const BatchProb *__restrict__ probs, const B
         const double d2 = heat3d7_plain_tile(P.f[parity], P.f[parity ^ 1], P.g, P.cc, P.cn, w.bx, w.by, w.bz);
         if (part) {
             const double s = block_sum_f64(d2, red);
-            if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) part[it] = s;
+            if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0) part[w.slot] = s;
         }
         __syncthreads();
     }

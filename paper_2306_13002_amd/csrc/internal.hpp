@@ -63,6 +63,7 @@ struct BatchProb {
 };
 struct BatchItem {
     int prob, bx, by, bz;
+    int slot;  // index of its residual partial within the class (problem-major, then z, y, x)
 };
 
 struct KindOps {
