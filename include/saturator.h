@@ -132,8 +132,11 @@ stencil_status sat_generate(const sat_program_desc *d, int32_t form, int32_t ext
 
 /* Rewrite, generate and compile (hipRTC) the program for one form; one
  * thread per interior (i, j) column, blocks of tile_x * tile_y threads (0 =
- * 64 x 4) over x and y and one z plane -- or, for SAT_ACCSAT_Z, `zblock`
- * planes per thread (0 = 32; ignored by the other forms). */
+ * 64 x 4) over x and y, each thread evaluating `zblock` consecutive planes
+ * of its column (0 = 1 plane; 32 for SAT_ACCSAT_Z).  With zblock > 1 the
+ * non-streaming forms issue every load again at each plane, and the planes
+ * shared with the previous one come from the caches; results do not depend
+ * on zblock. */
 stencil_status sat_plan(const sat_program_desc *d, int32_t form, int32_t tile_x, int32_t tile_y, int32_t zblock,
                         sat_plan_t *out);
 

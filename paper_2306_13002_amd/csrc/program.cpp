@@ -61,8 +61,7 @@ stencil_status read_desc(const sat_program_desc *d, sat::Program *p) {
 stencil_status check_shape(const sat::Program &p, int form, int *tx, int *ty, int *zb) {
     if (form < SAT_PLAIN || form > SAT_ACCSAT_Z) return fail(STENCIL_E_INVAL, "form %d is not a sat_form", form);
     if (*zb < 0) return fail(STENCIL_E_INVAL, "zblock must be >= 0");
-    if (form != SAT_ACCSAT_Z) *zb = 1;
-    else if (*zb == 0) *zb = 32;
+    if (*zb == 0) *zb = form == SAT_ACCSAT_Z ? 32 : 1;
     if (*tx == 0 && *ty == 0) {
         *tx = 64;
         *ty = 4;

@@ -1044,7 +1044,30 @@ std::string generate(const Program &p, int form, int extract, int tx, int ty, in
     std::snprintf(b, sizeof b, "struct SatArgs {\n    const double *in[%d];\n    double *out[%d];\n    double prm[%d];\n};\n",
                   NI, p.n_out, NP);
     s += b;
-    if (form != F_ACCSAT_Z) {
+    if (form != F_ACCSAT_Z && zb > 1) {
+        // z loop: a thread evaluates planes k0 .. k1-1 of its (i, j) column
+        // in turn; every load is issued again, and the planes shared with the
+        // previous step come from the caches (same CU, one plane earlier).
+        std::snprintf(b, sizeof b,
+                      "extern \"C\" __global__ __launch_bounds__(%d) void %s(SatArgs A) {\n"
+                      "    const int i = (int)(blockIdx.x * %d + threadIdx.x);\n"
+                      "    const int j = (int)(blockIdx.y * %d + threadIdx.y);\n"
+                      "    const int k0 = (int)blockIdx.z * %d, k1 = k0 + %d < %lld ? k0 + %d : %lld;\n"
+                      "    if (i >= %lld || j >= %lld) return;\n"
+                      "    long long o = (long long)(k0 + %d) * %lldLL + (long long)(j + %d) * %lldLL + (i + %d);\n"
+                      "#pragma unroll 1\n"
+                      "    for (int k = k0; k < k1; ++k, o += %lldLL) {\n",
+                      tx * ty, kernel_name(form), tx, ty, zb, zb, p.n[2], zb, p.n[2], p.n[0], p.n[1], p.radius, p.pz,
+                      p.radius, p.py, p.radius, p.pz);
+        s += b;
+        size_t pos = 0;
+        while (pos < E.body.size()) {
+            const size_t e = E.body.find('\n', pos);
+            s += "    " + E.body.substr(pos, e - pos + 1);
+            pos = e + 1;
+        }
+        s += "    }\n}\n";
+    } else if (form != F_ACCSAT_Z) {
         std::snprintf(b, sizeof b,
                       "extern \"C\" __global__ __launch_bounds__(%d) void %s(SatArgs A) {\n"
                       "    const int i = (int)(blockIdx.x * %d + threadIdx.x);\n"

@@ -90,6 +90,21 @@ def test_z_streaming_equals_accsat_bitwise(zb):
         assert np.array_equal(g, b)
 
 
+@pytest.mark.parametrize("form", ["plain", "cse", "cse_sat", "cse_bulk", "accsat"])
+@pytest.mark.parametrize("zb", [2, 3, 64])
+def test_z_loop_equals_one_plane_per_thread_bitwise(form, zb):
+    """The non-streaming forms with several planes per thread (a z loop that
+    issues every load again) give the one-plane-per-thread result bit for
+    bit, ragged z-blocks included (nz = 11)."""
+    prog = synth.lhs_program()
+    n = (37, 13, 11)
+    d = [dev(a) for a in synth.lhs_inputs(n)]
+    base = run(prog, n, d, synth.LHS_PARAMS, form)
+    got = run(prog, n, d, synth.LHS_PARAMS, form, zblock=zb)
+    for g, b in zip(got, base):
+        assert np.array_equal(g, b)
+
+
 @pytest.mark.parametrize("idx", range(4))
 def test_z_streaming_random_programs_with_radius_two(idx):
     """Programs reading z offsets -2..2 (windows of up to five planes)."""
@@ -142,8 +157,8 @@ def test_pitched_arrays():
         assert not np.any(g2)  # padding and halo untouched (zero-initialized)
 
 
-@pytest.mark.parametrize("form", ["plain", "accsat", "accsat_z"])
-def test_lhs_full_size_sampled_slabs(form):
+@pytest.mark.parametrize("form,zblock", [("plain", 0), ("accsat", 0), ("accsat", 16), ("accsat_z", 0)])
+def test_lhs_full_size_sampled_slabs(form, zblock):
     """The 162^3 workload at the benchmark's launch shape; the outputs of a
     point depend only on planes k-1..k+1, so the oracle runs on z-slabs of
     the inputs and is compared with the matching planes."""
@@ -151,7 +166,7 @@ def test_lhs_full_size_sampled_slabs(form):
     print(f"lhs full size {form}", flush=True)
     prog = synth.lhs_program()
     ins = synth.lhs_inputs(n)
-    got = run(prog, n, [dev(a) for a in ins], synth.LHS_PARAMS, form)
+    got = run(prog, n, [dev(a) for a in ins], synth.LHS_PARAMS, form, zblock=zblock)
     for k0, k1 in ((0, 2), (80, 82), (160, 162)):
         sub = [a[k0:k1 + 2] for a in ins]  # padded planes k0 .. k1+1 = interior k0-1 .. k1
         want = oracle.program(prog, sub, synth.LHS_PARAMS, (n[0], n[1], k1 - k0))
