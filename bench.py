@@ -532,6 +532,11 @@ def main():
         },
         "residual": main_r["resid"],
     }
+    if per_launch > 1 and roof["bound"] == "hbm":
+        # a launch advances per_launch sweeps for one pass of bytes: the rate a
+        # single-sweep kernel would need to match it (may exceed the peak)
+        out["roofline"]["sweep_equivalent"] = {"achieved": achieved * per_launch,
+                                               "frac": achieved * per_launch / HBM_PEAK_GBS}
     if len(forms) > 1:
         out["saturated_forms"] = {
             v: {"value": r["pts"] * a.steps / r["wall"], "us_per_sweep": r["sweep_ms"] * 1e3 / max(1, r["sweeps"]),

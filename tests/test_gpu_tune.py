@@ -93,6 +93,29 @@ def test_tune_cache_file_roundtrip(tmp_path):
     assert len(cache.read_text().strip().splitlines()) == 1
 
 
+def test_batch_class_tuning_cache_roundtrip(tmp_path):
+    """Batch classes are timed in place once per class (one cache line each,
+    keyed by the class's extents) and served from the file afterwards."""
+    cache = tmp_path / "tune.jsonl"
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2306_13002_amd.stencil import BatchPlan\n"
+            "b = BatchPlan([(40, 33, 35), (30, 41, 37), (90, 70, 66)], tune='exhaustive', variant='saturated')\n"
+            "print('CFG', b.config())\n") % ROOT
+    env = dict(os.environ, STENCIL_TUNE_CACHE=str(cache), STENCIL_LOG="1")
+    r1 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r1.returncode == 0, r1.stderr
+    keys = [json.loads(l)["key"] for l in cache.read_text().strip().splitlines()]
+    assert len(keys) == 2 and all(k.startswith("batch/k2/") for k in keys)  # two size classes
+    assert "tune batch class (2 problems)" in r1.stderr and "tune batch class (1 problems)" in r1.stderr
+    r2 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r2.returncode == 0, r2.stderr
+    assert "tune batch class" not in r2.stderr
+    cfg1 = [l for l in r1.stdout.splitlines() if l.startswith("CFG")]
+    cfg2 = [l for l in r2.stdout.splitlines() if l.startswith("CFG")]
+    assert cfg1 == cfg2
+    assert len(cache.read_text().strip().splitlines()) == 2
+
+
 def test_tuned_two_sweep_poisson19(dev):
     """The two-sweep form is tuned only when asked for; its pick is one of its
     own shapes and its result equals the single-sweep form at that shape."""
