@@ -308,6 +308,10 @@ struct Sat2Shape {
     static constexpr int EY0 = (RS + TX - 1) / TX;
     static constexpr int EY = (TX * (TY + EY0)) % 64 == 0 ? EY0 : EY0 + 1;  // whole waves
     static constexpr int NT = TX * (TY + EY);
+    // the loop unrolled by the ring size (constant slot addresses) takes
+    // 10-20 more VGPRs: measured 5 % faster at 64 x 8, slower at the other
+    // shapes (lost occupancy, or spills at 896 threads)
+    static constexpr bool UNROLL = TX == 64 && TY == 8;
 };
 
 template <int TX, int TY>
@@ -371,9 +375,9 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
     for (int z = zlo - 1; z <= zlo; ++z) {
         if (z < 0) continue;
         const float *pl = p + (long long)z * g.pz;
-        if (tile_t) r0[z & 3][e0_o] = ld_o ? pl[col_o] : 0.0f;
+        if (tile_t) r0[(z - zlo + 4) & 3][e0_o] = ld_o ? pl[col_o] : 0.0f;
         halo.load(pl);
-        halo.store(r0[z & 3]);
+        halo.store(r0[(z - zlo + 4) & 3]);
     }
     float ctr = ld_o ? p[col_o + (long long)(zlo + 1) * g.pz] : 0.0f;
     halo.load(p + (long long)(zlo + 1) * g.pz);
@@ -395,15 +399,17 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
 
     // Iteration zA: sweep 1 at plane zA, sweep 2 at plane zA-2 (its inputs,
     // sweep-1 planes zA-3 .. zA-1, were written in earlier iterations), so one
-    // barrier per plane separates every LDS write from its readers.
-    for (int zA = zlo; zA <= zhi + 1; ++zA) {
+    // barrier per plane separates every LDS write from its readers.  Ring
+    // slots are relative to zlo: plane z sits in slot (z - zlo) mod 4; SM,
+    // S0, SP, S2 are the slots of planes zA-1, zA, zA+1 and zA+2 (= zA-2).
+    auto step = [&](const int zA, const int SM, const int S0, const int SP, const int S2) {
         float cc[12];
 #pragma unroll
         for (int s = 0; s < 12; ++s) cc[s] = cf[s];
         if (zA <= zhi) {
             // stage p^t plane zA+1, then issue every load of the next plane
-            if (tile_t) r0[(zA + 1) & 3][e0_o] = ctr;
-            halo.store(r0[(zA + 1) & 3]);
+            if (tile_t) r0[SP][e0_o] = ctr;
+            halo.store(r0[SP]);
             if (zA < zhi) {
                 if (zA + 2 <= g.nz + 1) {
                     const float *pl = p + (long long)(zA + 2) * g.pz;
@@ -419,15 +425,15 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
         __syncthreads();
         if (zA <= zhi && has_a) {  // sweep 1 at plane zA: own cell or ring cell
             const bool zin = zA >= 1 && zA <= g.nz;
-            const float *m = r0[(zA - 1) & 3], *o = r0[zA & 3], *u = r0[(zA + 1) & 3];
+            const float *m = r0[SM], *o = r0[S0], *u = r0[SP];
             float v;
             if (zin && in_a) p19_update<W0>(m, o, u, e0_a, cc, omega, &v);
             else v = o[e0_a];
-            r1[zA & 3][e1_a] = v;
+            r1[S0][e1_a] = v;
         }
         const int zc = zA - 2;  // sweep 2 at plane zc, from sweep-1 planes zc-1 .. zc+1
         if (zc >= k0 + 1 && in_o) {
-            const float *m = r1[(zc - 1) & 3], *o = r1[zc & 3], *u = r1[(zc + 1) & 3];
+            const float *m = r1[SP], *o = r1[S2], *u = r1[SM];
             float v;
             const double ss = p19_update<W1>(m, o, u, e1_o, c2, omega, &v);
             pn[col_o + (long long)zc * g.pz] = v;
@@ -437,6 +443,19 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
         for (int s = 0; s < 12; ++s) {
             c2[s] = c1[s];
             c1[s] = cc[s];
+        }
+    };
+    if (S::UNROLL) {  // four planes per trip: every slot a compile-time constant
+        for (int zA = zlo; zA <= zhi + 1; zA += 4) {
+            step(zA, 3, 0, 1, 2);
+            if (zA + 1 <= zhi + 1) step(zA + 1, 0, 1, 2, 3);
+            if (zA + 2 <= zhi + 1) step(zA + 2, 1, 2, 3, 0);
+            if (zA + 3 <= zhi + 1) step(zA + 3, 2, 3, 0, 1);
+        }
+    } else {
+        for (int zA = zlo; zA <= zhi + 1; ++zA) {
+            const int q = (zA - zlo) & 3;
+            step(zA, (q + 3) & 3, q, (q + 1) & 3, (q + 2) & 3);
         }
     }
     if (part) {
