@@ -119,8 +119,10 @@ stencil_status tune_class(const std::vector<int> &members, const std::vector<Geo
         const long long n = g.pz * (g.nz + 2);
         for (int f = 0; f < 2; ++f) {
             void *q = nullptr;
-            if ((e = hipMalloc(&q, sizeof(double) * (size_t)n)) != hipSuccess)
+            if ((e = hipMalloc(&q, sizeof(double) * (size_t)n)) != hipSuccess) {
+                (void)hipGetLastError();  // leave no sticky error for later launches
                 return fail(STENCIL_E_NOMEM, "class tuning buffers: %s", hipGetErrorString(e));
+            }
             sc.ptrs.push_back(q);
             if ((e = launch_fill(q, n, 8, 1.0, sc.s)) != hipSuccess) return hip_fail(e, "fill");
             probs[k].f[f] = (double *)q;
@@ -143,10 +145,15 @@ stencil_status tune_class(const std::vector<int> &members, const std::vector<Geo
         max_items = std::max(max_items, (size_t)n);
     }
     void *d_probs = nullptr, *d_items = nullptr;
-    if ((e = hipMalloc(&d_probs, sizeof(BatchProb) * m)) != hipSuccess) return fail(STENCIL_E_NOMEM, "class tuning");
-    sc.ptrs.push_back(d_probs);
-    if ((e = hipMalloc(&d_items, sizeof(BatchItem) * max_items)) != hipSuccess)
+    if ((e = hipMalloc(&d_probs, sizeof(BatchProb) * m)) != hipSuccess) {
+        (void)hipGetLastError();
         return fail(STENCIL_E_NOMEM, "class tuning");
+    }
+    sc.ptrs.push_back(d_probs);
+    if ((e = hipMalloc(&d_items, sizeof(BatchItem) * max_items)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(STENCIL_E_NOMEM, "class tuning");
+    }
     sc.ptrs.push_back(d_items);
     if ((e = hipMemcpyAsync(d_probs, probs.data(), sizeof(BatchProb) * m, hipMemcpyHostToDevice, sc.s)) != hipSuccess)
         return hip_fail(e, "problem table upload");
@@ -405,18 +412,32 @@ extern "C" stencil_status stencil_plan_batch(const stencil_desc *ds, int32_t cou
         BatchClass C;
         const bool open = !is_point_form(d.variant) &&
                           (d.variant == STENCIL_AUTO || !d.tile_x || !d.tile_y || !d.zblock);
+        bool tuned = false;
         if (ds[0].tune != STENCIL_TUNE_FIXED && open) {  // EXHAUSTIVE and MODEL: timed in place
             const TuneRequest rq{d.variant, d.tile_x, d.tile_y, d.zblock, 1};
             const std::string key = class_key(members, geoms, rq);
             TuneEntry te{};
-            if (!tune_lookup(key, &te)) {
-                if ((st = tune_class(members, geoms, ds[rep[c]].coef[0], ds[rep[c]].coef[1], rq, &te)) != STENCIL_OK)
+            if (tune_lookup(key, &te)) {
+                tuned = true;
+            } else {
+                st = tune_class(members, geoms, ds[rep[c]].coef[0], ds[rep[c]].coef[1], rq, &te);
+                if (st == STENCIL_OK) {
+                    tune_store(key, te);
+                    tuned = true;
+                } else if (st == STENCIL_E_NOMEM) {  // no room for the class's scratch grids
+                    logf("%s; tuning class %d on its largest problem alone", stencil_last_error(), c);
+                    d.tune = ds[0].tune;
+                    st = STENCIL_OK;
+                } else {
                     break;
-                tune_store(key, te);
+                }
             }
-            C.variant = te.variant;
-            C.tile = te.tile;
-        } else {
+            if (tuned) {
+                C.variant = te.variant;
+                C.tile = te.tile;
+            }
+        }
+        if (!tuned) {
             stencil_plan_t rp = nullptr;
             if ((st = stencil_plan(&d, &rp)) != STENCIL_OK) break;
             C.variant = rp->variant;
