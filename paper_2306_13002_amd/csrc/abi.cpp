@@ -49,6 +49,9 @@ stencil_status fail(stencil_status st, const char *fmt, ...) {
     va_end(ap);
     g_err = buf;
     if (log_on()) std::fprintf(stderr, "[stencil] error %d: %s\n", (int)st, buf);
+    // a failed allocation leaves its error as the runtime's last error; clear
+    // it so that a later launch check does not report it as a launch failure
+    if (st == STENCIL_E_NOMEM) (void)hipGetLastError();
     return st;
 }
 

@@ -119,10 +119,8 @@ stencil_status tune_class(const std::vector<int> &members, const std::vector<Geo
         const long long n = g.pz * (g.nz + 2);
         for (int f = 0; f < 2; ++f) {
             void *q = nullptr;
-            if ((e = hipMalloc(&q, sizeof(double) * (size_t)n)) != hipSuccess) {
-                (void)hipGetLastError();  // leave no sticky error for later launches
+            if ((e = hipMalloc(&q, sizeof(double) * (size_t)n)) != hipSuccess)
                 return fail(STENCIL_E_NOMEM, "class tuning buffers: %s", hipGetErrorString(e));
-            }
             sc.ptrs.push_back(q);
             if ((e = launch_fill(q, n, 8, 1.0, sc.s)) != hipSuccess) return hip_fail(e, "fill");
             probs[k].f[f] = (double *)q;
@@ -145,15 +143,10 @@ stencil_status tune_class(const std::vector<int> &members, const std::vector<Geo
         max_items = std::max(max_items, (size_t)n);
     }
     void *d_probs = nullptr, *d_items = nullptr;
-    if ((e = hipMalloc(&d_probs, sizeof(BatchProb) * m)) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(STENCIL_E_NOMEM, "class tuning");
-    }
+    if ((e = hipMalloc(&d_probs, sizeof(BatchProb) * m)) != hipSuccess) return fail(STENCIL_E_NOMEM, "class tuning");
     sc.ptrs.push_back(d_probs);
-    if ((e = hipMalloc(&d_items, sizeof(BatchItem) * max_items)) != hipSuccess) {
-        (void)hipGetLastError();
+    if ((e = hipMalloc(&d_items, sizeof(BatchItem) * max_items)) != hipSuccess)
         return fail(STENCIL_E_NOMEM, "class tuning");
-    }
     sc.ptrs.push_back(d_items);
     if ((e = hipMemcpyAsync(d_probs, probs.data(), sizeof(BatchProb) * m, hipMemcpyHostToDevice, sc.s)) != hipSuccess)
         return hip_fail(e, "problem table upload");
