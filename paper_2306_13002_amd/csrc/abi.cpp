@@ -86,6 +86,7 @@ int elem_bytes(int dtype) { return dtype == STENCIL_F32 ? 4 : 8; }
 // picked from launch-shape sweeps on MI355X at the workload sizes.
 Tile default_tile(int kind, int variant, const Geom &g) {
     if (variant == V_PLAIN) return kind == STENCIL_HEAT2D5 ? Tile{64, 4, 1} : Tile{128, 8, 1};
+    if (variant == V_SAT2 && kind == STENCIL_POISSON19) return Tile{64, 8, g.nz < 32 ? g.nz : 32};
     switch (kind) {
     case STENCIL_HEAT3D7: return Tile{32, 8, g.nz < 8 ? g.nz : 8};
     case STENCIL_POISSON19: return Tile{128, 4, g.nz < 32 ? g.nz : 32};
@@ -356,7 +357,7 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     }
     int v = d->variant;
     if (v == STENCIL_AUTO) v = has_sat ? V_SATURATED : V_PLAIN;
-    Tile t = default_tile(p->kind, is_point_form(v) ? V_PLAIN : (v == V_SAT2 ? V_SATURATED : v), p->g);
+    Tile t = default_tile(p->kind, is_point_form(v) ? V_PLAIN : v, p->g);
     if (d->tile_x) t.tx = d->tile_x;
     if (d->tile_y) t.ty = d->tile_y;
     if (d->zblock) t.tz = d->zblock;

@@ -122,6 +122,26 @@ def test_batch_tuned_workload(dev):
         assert maxrel(inner(fs[i][0].cpu().numpy(), 1), inner(want, 1)) <= 1e-12
 
 
+def test_batch_two_sweep_tuned_workload(dev):
+    """The 64-problem workload with two-sweep classes tuned in place (the
+    benchmark's configuration), against 64 separate plain runs."""
+    from paper_2306_13002_amd.stencil import BatchPlan
+    sizes = synth.heat3d7_batch_sizes()
+    us, fs = fields_for(sizes, dev, stream0=1)
+    bp = BatchPlan(sizes, tune="exhaustive", variant="saturated_t2")
+    bp.run(fs, iterations=50)
+    res = bp.residuals()
+    bp.close()
+    for i, n in enumerate(sizes):
+        want, wr = single(n, us[i], 50, dev, variant="plain")
+        got = fs[i][0].cpu().numpy()
+        assert maxrel(inner(got, 1), inner(want, 1)) <= 1e-12, f"problem {i}"
+        assert abs(res[i] - wr) <= 1e-10 * wr
+    for i in sorted(range(len(sizes)), key=lambda b: np.prod(sizes[b]))[:2]:
+        want, _ = oracle.heat(us[i], 50, 0.4, 0.1)
+        assert maxrel(inner(fs[i][0].cpu().numpy(), 1), inner(want, 1)) <= 1e-12
+
+
 def test_batch_two_sweep_equals_single_sweep_batch(dev):
     """A batch whose classes run two sweeps per launch gives the single-sweep
     batch's result bit for bit (odd T: one single sweep first)."""

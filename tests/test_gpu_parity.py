@@ -133,6 +133,22 @@ def test_heat3d7_two_sweep_vs_oracle(dev):
     assert abs(gr - wr) <= 1e-10 * wr
 
 
+@pytest.mark.parametrize("variant", ["plain", "saturated", "saturated_t2"])
+def test_heat3d7_workload_full(dev, variant):
+    """The 160^3 grid, T = 50, at the tuned launch shape the benchmark times."""
+    n = (160, 160, 160)
+    print(f"heat3d7 160^3 {variant}", flush=True)
+    u0 = synth.heat3d7_input(*n)
+    want, wr = oracle.heat(u0, 50, 0.4, 0.1)
+    got, gr = run_jacobi("heat3d7", u0, n, dev, 50, coef=(0.4, 0.1), variant=variant, tune="exhaustive")
+    if variant == "plain":
+        assert np.array_equal(got, want)
+    else:
+        assert maxrel(inner(got, 1), inner(want, 1)) <= 1e-12
+    assert np.array_equal(got[0], u0[0]) and np.array_equal(got[:, -1], u0[:, -1])
+    assert abs(gr - wr) <= 1e-10 * wr
+
+
 @pytest.mark.parametrize("variant", ["plain", "saturated"])
 def test_heat3d7_periodic(dev, variant):
     u0 = synth.heat3d7_input(33, 20, 17, stream=5)
@@ -216,20 +232,22 @@ def test_poisson19_two_sweep_vs_oracle(dev, tile):
     assert np.array_equal(got[0], p0[0]) and np.array_equal(got[:, 0], p0[:, 0])
 
 
-@pytest.mark.parametrize("variant", ["plain", "saturated", "saturated_t2"])
-def test_poisson19_workload_full(dev, variant):
+@pytest.mark.parametrize("variant,tile", [("plain", (0, 0, 0)), ("saturated", (0, 0, 0)), ("saturated_t2", (0, 0, 0)),
+                                          ("saturated_t2", (64, 8, 32)), ("saturated_t2", (128, 4, 32))])
+def test_poisson19_workload_full(dev, variant, tile):
     # the 129 x 129 x 257 (boundary included) workload, T = 20, as benchmarked
+    # (default shape, and the two-sweep shapes the tuner picks)
     p0, cf = synth.poisson19_inputs()
     n = (127, 127, 255)
     w64, g64 = oracle.poisson19(p0, cf, 0.8, 20, mode="F64")
     w32, g32 = oracle.poisson19(p0, cf, 0.8, 20, mode="F32STORE")
-    got, gg = run_jacobi("poisson19", p0, n, dev, 20, coefs=cf, variant=variant, omega=0.8)
+    got, gg = run_jacobi("poisson19", p0, n, dev, 20, coefs=cf, variant=variant, omega=0.8, tile=tile)
     assert maxrel(inner(got, 1), inner(w64, 1)) <= 1e-5
     assert abs(gg - g32) <= 1e-5 * g32
     if variant == "plain":
         assert np.array_equal(got.astype(np.float64), w32)
     # first sweep: closed form of the residual
-    p1 = Plan("poisson19", n, variant=variant, omega=0.8)
+    p1 = Plan("poisson19", n, variant=variant, omega=0.8, tile=tile)
     f = [_dev(p0, dev), _nan_like(p0, dev)]
     p1.run(f, [_dev(c, dev) for c in cf], iterations=1)
     g1 = p1.residual()
