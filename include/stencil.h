@@ -183,7 +183,11 @@ stencil_status stencil_plan_batch(const stencil_desc *ds, int32_t count, stencil
  *   layout in the order a0 a1 a2 a3 b0 b1 b2 c0 c1 c2 bnd wrk1;
  *   WAVE25: {vsq} (F64 grid); others: NULL.
  * Every pointer must be aligned to its element size.  iterations == 0 is a
- * no-op.  The residual of the last sweep is kept for stencil_residual. */
+ * no-op.  The residual of the last sweep is kept for stencil_residual.
+ * With graphs enabled (stencil_plan_use_graphs), a run that repeats the
+ * previous run's iteration count and pointers is captured into HIP graphs
+ * (halo copy, sweeps, final copy) and replayed from them while the same
+ * runs keep arriving: the same kernels and results. */
 stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *const *coef_arrays,
                            int32_t iterations, void *stream);
 
@@ -202,6 +206,18 @@ stencil_status stencil_residuals(stencil_plan_t p, double *host_out, int32_t cou
  * tile_map is reported as 1 (natural) or 2 (XCD-chunked). */
 stencil_status stencil_plan_config(stencil_plan_t p, int32_t *variant, int32_t *tile_x, int32_t *tile_y,
                                    int32_t *zblock, int32_t *tile_map);
+
+/* Graph replay of repeated runs for a single plan (off by default; GENERIC
+ * and batched plans: E_UNSUPPORTED, batches always run as graphs).  One
+ * graph launch replaces a launch per sweep, which saves host time when the
+ * caller cannot stay ahead of the GPU; on MI355X the graph's sweeps run no
+ * faster than the same launches on a stream.  A capture failure leaves the
+ * plan running eagerly. */
+stencil_status stencil_plan_use_graphs(stencil_plan_t p, int32_t enable);
+
+/* Iteration count of the run a single plan replays from captured graphs (see
+ * stencil_run), or 0 if it holds none. */
+stencil_status stencil_plan_graph(stencil_plan_t p, int32_t *iterations);
 
 /* Sweep timing.  When enabled, stencil_run records HIP events on its stream
  * around its sweep launches (after the halo copy, before any tail copy);

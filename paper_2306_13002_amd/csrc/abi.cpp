@@ -294,6 +294,12 @@ void free_plan(stencil_plan_s *p) {
     if (p->d_red) (void)hipFree(p->d_red);
     if (p->d_tab) (void)hipFree(p->d_tab);
     free_batch(p->batch);
+    if (p->rg) {
+        for (hipGraphExec_t x : p->rg->x)
+            if (x) (void)hipGraphExecDestroy(x);
+        if (p->rg->cap) (void)hipStreamDestroy(p->rg->cap);
+        delete p->rg;
+    }
     delete p->rtc;
     if (p->d_result) (void)hipFree(p->d_result);
     if (p->h_result) (void)hipHostFree(p->h_result);
@@ -368,6 +374,87 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     p->tile = t;
     p->remap = d->tile_map ? (d->tile_map == 2) : default_remap(p->kind);
     return STENCIL_OK;
+}
+
+// The three parts of a run on stream s (enqueued eagerly or under capture).
+// Jacobi kinds first copy the state's halo into the scratch grid.
+hipError_t run_pre(stencil_plan_s *p, void *const *fields, hipStream_t s) {
+    if (p->kind == STENCIL_WAVE25 || p->bc != STENCIL_BC_DIRICHLET) return hipSuccess;
+    return launch_halo_copy(fields[0], fields[1], elem_bytes(p->dtype), p->g, p->rz, s);
+}
+
+// Jacobi kinds read fields[0] first; the leapfrog reads the newer level
+// fields[1] and overwrites the older fields[0] in place.  A launch of the
+// two-sweep form advances two sweeps; an odd count starts with one single
+// saturated sweep at the same shape, so the last launch (the one that leaves
+// the residual partials) is always of the plan's form.
+hipError_t run_sweeps(stencil_plan_s *p, void *const *fields, SweepArgs a, int iterations, hipStream_t s,
+                      int *launches) {
+    const bool wave = p->kind == STENCIL_WAVE25;
+    const int eb = elem_bytes(p->dtype);
+    void *src = wave ? fields[1] : fields[0], *dst = wave ? fields[0] : fields[1];
+    const int per = sweeps_per_launch(p->variant);
+    hipError_t e;
+    *launches = 0;
+    for (int t = 0; t < iterations;) {
+        if (p->bc == STENCIL_BC_PERIODIC && (e = launch_periodic_fill(src, eb, p->g, p->rz, s)) != hipSuccess)
+            return e;
+        const int v = (t == 0 && (iterations % per)) ? V_SATURATED : p->variant;
+        const int adv = sweeps_per_launch(v);
+        a.src = src;
+        a.dst = dst;
+        a.part = (t + adv == iterations) ? p->d_part : nullptr;
+        if ((e = p->ops->launch(v, p->tile, a, s)) != hipSuccess) return e;
+        t += adv;
+        ++*launches;
+        std::swap(src, dst);
+    }
+    return hipSuccess;
+}
+
+// An odd launch count leaves a Jacobi result in the scratch grid: copy it back.
+hipError_t run_post(stencil_plan_s *p, void *const *fields, int launches, hipStream_t s) {
+    if (p->kind == STENCIL_WAVE25 || !(launches & 1)) return hipSuccess;
+    return launch_interior_copy(fields[1], fields[0], elem_bytes(p->dtype), p->g, p->rz, s);
+}
+
+// Capture the three parts into p->rg->x (replacing earlier graphs).  Every
+// node is a kernel launch.  On failure no graph is kept and no error is left.
+hipError_t capture_run(stencil_plan_s *p, void *const *fields, const SweepArgs &a, int iterations) {
+    RunGraphs *rg = p->rg;
+    for (hipGraphExec_t &x : rg->x) {
+        if (x) (void)hipGraphExecDestroy(x);
+        x = nullptr;
+    }
+    rg->T = -1;
+    hipError_t e = hipSuccess;
+    if (!rg->cap && (e = hipStreamCreate(&rg->cap)) != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
+    int launches = 0;
+    for (int part = 0; part < 3 && e == hipSuccess; ++part) {
+        if ((e = hipStreamBeginCapture(rg->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) break;
+        const hipError_t le = part == 0 ? run_pre(p, fields, rg->cap)
+                              : part == 1 ? run_sweeps(p, fields, a, iterations, rg->cap, &launches)
+                                          : run_post(p, fields, launches, rg->cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(rg->cap, &g);
+        if (le != hipSuccess) e = le;
+        size_t n = 0;
+        if (e == hipSuccess && g) e = hipGraphGetNodes(g, nullptr, &n);
+        if (e == hipSuccess && n > 0) e = hipGraphInstantiate(&rg->x[part], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+    }
+    if (e != hipSuccess || !rg->x[1]) {
+        for (hipGraphExec_t &x : rg->x) {
+            if (x) (void)hipGraphExecDestroy(x);
+            x = nullptr;
+        }
+        (void)hipGetLastError();
+        return e != hipSuccess ? e : hipErrorUnknown;
+    }
+    return hipSuccess;
 }
 
 }  // namespace stn
@@ -459,43 +546,49 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
     hipStream_t s = (hipStream_t)stream_;
     hipError_t e;
     p->has_resid = false;
-    const bool wave = p->kind == STENCIL_WAVE25;
-    if (!wave && p->bc == STENCIL_BC_DIRICHLET) {
-        if ((e = launch_halo_copy(fields[0], fields[1], eb, p->g, p->rz, s)) != hipSuccess)
-            return hip_fail(e, "halo copy launch");
+    std::vector<const void *> sig{fields[0], fields[1]};
+    const int ncoef = p->kind == STENCIL_POISSON19 ? 12 : (p->kind == STENCIL_WAVE25 ? 1 : 0);
+    for (int c = 0; c < ncoef; ++c) sig.push_back(coef_arrays[c]);
+    RunGraphs *rg = (p->rg && p->rg->on && !p->rg->off) ? p->rg : nullptr;
+    bool replay = false;
+    if (rg) {
+        if (rg->x[1] && rg->T == iterations && rg->sig == sig) {
+            replay = true;
+        } else if (rg->last_T == iterations && rg->last == sig) {
+            if (capture_run(p, fields, a, iterations) == hipSuccess) {
+                rg->T = iterations;
+                rg->sig = sig;
+                replay = true;
+                logf("run graph captured: kind=%d T=%d", p->kind, iterations);
+            } else {
+                logf("run graph capture failed; running eagerly from now on");
+                rg->off = true;
+            }
+        }
+        rg->last_T = iterations;
+        rg->last = sig;
     }
-    if (p->profiling && (e = hipEventRecord(p->ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    // Jacobi kinds read fields[0] first; the leapfrog reads the newer level
-    // fields[1] and overwrites the older fields[0] in place.
-    void *src = wave ? fields[1] : fields[0], *dst = wave ? fields[0] : fields[1];
-    // A launch of the two-sweep form advances two sweeps; an odd count starts
-    // with one single saturated sweep at the same shape, so the last launch
-    // (the one that leaves the residual partials) is always of the plan's form.
-    const int per = sweeps_per_launch(p->variant);
-    int launches = 0;
-    for (int t = 0; t < iterations;) {
-        if (p->bc == STENCIL_BC_PERIODIC && (e = launch_periodic_fill(src, eb, p->g, p->rz, s)) != hipSuccess)
-            return hip_fail(e, "periodic fill launch");
-        const int v = (t == 0 && (iterations % per)) ? V_SATURATED : p->variant;
-        const int adv = sweeps_per_launch(v);
-        a.src = src;
-        a.dst = dst;
-        a.part = (t + adv == iterations) ? p->d_part : nullptr;
-        if ((e = p->ops->launch(v, p->tile, a, s)) != hipSuccess) return hip_fail(e, "sweep launch");
-        t += adv;
-        ++launches;
-        void *tmp = src;
-        src = dst;
-        dst = tmp;
-    }
-    if (p->profiling) {
-        if ((e = hipEventRecord(p->ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-        p->prof_sweeps = iterations;
-        p->prof_valid = true;
-    }
-    if (!wave && (launches & 1)) {
-        if ((e = launch_interior_copy(fields[1], fields[0], eb, p->g, p->rz, s)) != hipSuccess)
-            return hip_fail(e, "tail copy launch");
+    if (replay) {
+        if (rg->x[0] && (e = hipGraphLaunch(rg->x[0], s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        if (p->profiling && (e = hipEventRecord(p->ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if ((e = hipGraphLaunch(rg->x[1], s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        if (p->profiling) {
+            if ((e = hipEventRecord(p->ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            p->prof_sweeps = iterations;
+            p->prof_valid = true;
+        }
+        if (rg->x[2] && (e = hipGraphLaunch(rg->x[2], s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    } else {
+        if ((e = run_pre(p, fields, s)) != hipSuccess) return hip_fail(e, "halo copy launch");
+        if (p->profiling && (e = hipEventRecord(p->ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        int launches = 0;
+        if ((e = run_sweeps(p, fields, a, iterations, s, &launches)) != hipSuccess) return hip_fail(e, "sweep launch");
+        if (p->profiling) {
+            if ((e = hipEventRecord(p->ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            p->prof_sweeps = iterations;
+            p->prof_valid = true;
+        }
+        if ((e = run_post(p, fields, launches, s)) != hipSuccess) return hip_fail(e, "tail copy launch");
     }
     p->has_resid = true;
     return STENCIL_OK;
@@ -537,6 +630,22 @@ stencil_status stencil_plan_config(stencil_plan_t p, int32_t *variant, int32_t *
     if (tile_y) *tile_y = p->tile.ty;
     if (zblock) *zblock = p->tile.tz;
     if (tile_map) *tile_map = p->remap ? 2 : 1;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_plan_use_graphs(stencil_plan_t p, int32_t enable) {
+    if (!p) return fail(STENCIL_E_INVAL, "plan is NULL");
+    if (p->batch) return fail(STENCIL_E_UNSUPPORTED, "batched plans always run as graphs");
+    // GENERIC launches generated kernels through the module API: always eager
+    if (p->kind == STENCIL_GENERIC) return fail(STENCIL_E_UNSUPPORTED, "GENERIC plans run eagerly");
+    if (!p->rg && !(p->rg = new (std::nothrow) RunGraphs())) return fail(STENCIL_E_NOMEM, "host allocation failed");
+    p->rg->on = enable != 0;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_plan_graph(stencil_plan_t p, int32_t *iterations) {
+    if (!p || !iterations) return fail(STENCIL_E_INVAL, "plan and iterations are required");
+    *iterations = (p->rg && p->rg->x[1]) ? p->rg->T : 0;
     return STENCIL_OK;
 }
 

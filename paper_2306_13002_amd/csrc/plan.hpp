@@ -36,6 +36,20 @@ struct BatchState {
     std::vector<hipEvent_t> evs;        // fork + one join per class
 };
 
+// Graphs of one run of a single plan: the halo copy, the sweeps and the odd-T
+// copy (an empty part has no graph), captured when the same iteration count
+// and pointers arrive twice in a row and replayed while they keep arriving.
+struct RunGraphs {
+    hipStream_t cap = nullptr;                          // capture stream
+    hipGraphExec_t x[3] = {nullptr, nullptr, nullptr};  // pre, sweeps, post
+    int T = -1;
+    std::vector<const void *> sig;   // pointers of the captured run
+    std::vector<const void *> last;  // pointers of the previous run
+    int last_T = -1;
+    bool on = false;                 // enabled by stencil_plan_use_graphs
+    bool off = false;                // a capture failed: eager runs only
+};
+
 struct stencil_plan_s {
     int kind = 0, dtype = 0, bc = 0;
     int variant = 0;            // resolved form (stn::Variant)
@@ -62,5 +76,6 @@ struct stencil_plan_s {
     stn::RtcSpec *rtc = nullptr; // GENERIC: spec of the generated saturated kernels
     bool tuned = false;          // configuration came from the autotuner
     BatchState *batch = nullptr; // non-null for plans made by stencil_plan_batch
+    RunGraphs *rg = nullptr;     // single plans: captured runs
     stn::StencilInfo info{};     // static description (cost-model features)
 };

@@ -71,6 +71,8 @@ def lib():
         L.stencil_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
         L.stencil_residual.argtypes = [vp, dp, vp]
         L.stencil_plan_config.argtypes = [vp] + [ctypes.POINTER(i32)] * 5
+        L.stencil_plan_graph.argtypes = [vp, ctypes.POINTER(i32)]
+        L.stencil_plan_use_graphs.argtypes = [vp, i32]
         L.stencil_profile_enable.argtypes = [vp, i32]
         L.stencil_profile_read.argtypes = [vp, dp, ctypes.POINTER(i32)]
         L.stencil_destroy.argtypes = [vp]
@@ -83,7 +85,8 @@ def lib():
         L.stencil_mlp_predict.argtypes = [fp, fp, i32, fp, vp]
         L.stencil_prepare.argtypes = [ctypes.POINTER(StencilDesc)]
         L.stencil_prepare.restype = ctypes.c_int
-        for f in (L.stencil_plan, L.stencil_run, L.stencil_residual, L.stencil_plan_config,
+        for f in (L.stencil_plan, L.stencil_run, L.stencil_residual, L.stencil_plan_config, L.stencil_plan_graph,
+                  L.stencil_plan_use_graphs,
                   L.stencil_profile_enable, L.stencil_profile_read, L.stencil_destroy, L.stencil_plan_batch,
                   L.stencil_residuals, L.stencil_candidates, L.stencil_features, L.stencil_mlp_train,
                   L.stencil_mlp_predict):
@@ -240,6 +243,16 @@ class Plan:
                                          ctypes.byref(m)))
         return {"variant": VARIANT_NAMES[v.value], "tile": (tx.value, ty.value, zb.value),
                 "tile_map": TILE_MAP_NAMES.get(m.value, m.value)}
+
+    def use_graphs(self, enable: bool = True):
+        """Replay repeated identical runs from captured HIP graphs."""
+        _check(lib().stencil_plan_use_graphs(self._h, 1 if enable else 0))
+
+    def graph_iterations(self) -> int:
+        """Iteration count of the run replayed from captured graphs (0: none)."""
+        t = ctypes.c_int32()
+        _check(lib().stencil_plan_graph(self._h, ctypes.byref(t)))
+        return t.value
 
     def profile(self, enable: bool = True):
         _check(lib().stencil_profile_enable(self._h, 1 if enable else 0))
