@@ -218,6 +218,33 @@ def test_poisson19_two_sweep_equals_saturated_bitwise(dev, tile, zb, remap):
         assert gg == gr, T
 
 
+TINY = [(1, 1, 1), (3, 2, 1), (5, 1, 2), (2, 7, 3), (70, 1, 1), (1, 40, 5), (65, 9, 2)]
+
+
+@pytest.mark.parametrize("n", TINY)
+@pytest.mark.parametrize("zb", [1, 2, 64])
+def test_two_sweep_forms_on_degenerate_grids(dev, n, zb):
+    """One- and two-cell extents, single planes, grids smaller than a tile:
+    both two-sweep forms equal their single-sweep forms bit for bit and the
+    oracle within tolerance, for T = 1..4."""
+    u0 = synth.heat3d7_input(*n, stream=40)
+    pp, cf = synth.poisson19_random_inputs((n[2] + 2, n[1] + 2, n[0] + 2), seed=40)
+    for T in (1, 2, 3, 4):
+        print(f"degenerate n={n} zb={zb} T={T}", flush=True)
+        ref, gr = run_jacobi("heat3d7", u0, n, dev, T, coef=(0.4, 0.1), variant="saturated", tile=(32, 8, zb))
+        got, gg = run_jacobi("heat3d7", u0, n, dev, T, coef=(0.4, 0.1), variant="saturated_t2", tile=(32, 8, zb))
+        assert np.array_equal(got, ref) and gg == gr, ("heat3d7", T)
+        want, wr = oracle.heat(u0, T, 0.4, 0.1)
+        assert maxrel(inner(got, 1), inner(want, 1)) <= 1e-12
+        assert abs(gg - wr) <= 1e-10 * wr or (wr == 0 and gg == 0)
+        ref, gr = run_jacobi("poisson19", pp, n, dev, T, coefs=cf, variant="saturated", tile=(64, 8, zb), omega=0.8)
+        got, gg = run_jacobi("poisson19", pp, n, dev, T, coefs=cf, variant="saturated_t2", tile=(64, 8, zb),
+                             omega=0.8)
+        assert np.array_equal(got, ref) and gg == gr, ("poisson19", T)
+        w64, _ = oracle.poisson19(pp, cf, 0.8, T, mode="F64")
+        assert maxrel(inner(got.astype(np.float64), 1), inner(w64, 1)) <= 1e-5
+
+
 @pytest.mark.parametrize("tile", [(128, 4), (64, 8), (32, 4)])
 def test_poisson19_two_sweep_vs_oracle(dev, tile):
     p0, cf = _p19_inputs(seed=6)
