@@ -193,10 +193,21 @@ bool load_model(std::vector<float> &model) {
 
 }  // namespace
 
+// The cost model's candidates: the exhaustive tuner's, without the two-sweep
+// form unless it is asked for by name (the model's features describe only
+// the plain and single-sweep saturated forms, and its training campaign has
+// no timings of the two-sweep form).
+std::vector<Cand> model_candidates(const KindOps *ops, int kind, const Geom &g, const TuneRequest &rq) {
+    std::vector<Cand> c = tune_candidates(ops, kind, g, rq);
+    if (rq.variant != V_SAT2)
+        c.erase(std::remove_if(c.begin(), c.end(), [](const Cand &x) { return x.variant == V_SAT2; }), c.end());
+    return c;
+}
+
 stencil_status tune_model(stencil_plan_s *p, const TuneRequest &rq, TuneEntry *best) {
     std::vector<float> model;
     if (!load_model(model)) return fail(STENCIL_E_STATE, "no usable cost model at %s", model_path().c_str());
-    const std::vector<Cand> cands = tune_candidates(p->ops, p->kind, p->g, rq);
+    const std::vector<Cand> cands = model_candidates(p->ops, p->kind, p->g, rq);
     if (cands.empty()) return fail(STENCIL_E_UNSUPPORTED, "no launch shape matches the requested tile fields");
     std::vector<float> X(cands.size() * 24), y(cands.size());
     for (size_t i = 0; i < cands.size(); ++i) cost_features(p->info, cands[i], &X[i * 24]);
@@ -229,7 +240,7 @@ stencil_status stencil_candidates(const stencil_desc *d, int32_t max, int32_t *o
     stencil_status st = validate_desc(d, g, rz);
     if (st != STENCIL_OK) return st;
     TuneRequest rq{d->variant, d->tile_x, d->tile_y, d->zblock, d->tile_map};
-    const std::vector<Cand> c = tune_candidates(ops_for(d->kind), d->kind, g, rq);
+    const std::vector<Cand> c = model_candidates(ops_for(d->kind), d->kind, g, rq);
     *n = (int32_t)c.size();
     for (int i = 0; i < (int)c.size() && i < max; ++i) {
         int32_t *o = out + 5 * i;

@@ -87,7 +87,7 @@ std::vector<Cand> tune_candidates(const KindOps *ops, int kind, const Geom &g, c
     if (want_v(V_PLAIN))
         for (const Tile &t : kPlainTiles)
             if (ops->tile_ok(V_PLAIN, t) && tile_fits(t)) out.push_back({V_PLAIN, t, 0});
-    if (rq.variant == V_SAT2 && ops->sat2_tiles) {  // only when asked for: see STENCIL_SATURATED_T2
+    if ((rq.variant == V_SAT2 || rq.variant == STENCIL_AUTO) && ops->sat2_tiles) {
         Tile st[64];
         const int ns = ops->sat2_tiles(st, 64);
         std::vector<int> zbs;
@@ -145,7 +145,9 @@ struct Buffers {
 
 std::string tune_key(const stencil_plan_s *p, const TuneRequest &rq) {
     char buf[512];
-    std::snprintf(buf, sizeof buf, "k%d/d%d/bc%d/n%dx%dx%d/r%d/py%lld/pz%lld/v%d/t%d,%d,%d,%d/h%08x", p->kind,
+    // "/c2": candidate set 2 (AUTO includes the two-sweep form); entries of
+    // earlier sets are not reused
+    std::snprintf(buf, sizeof buf, "k%d/d%d/bc%d/n%dx%dx%d/r%d/py%lld/pz%lld/v%d/t%d,%d,%d,%d/h%08x/c2", p->kind,
                   p->dtype, p->bc, p->g.nx, p->g.ny, p->g.nz, p->g.r, p->g.py, p->g.pz, rq.variant, rq.tile_x,
                   rq.tile_y, rq.zblock, rq.tile_map, p->taps_hash);
     return buf;
