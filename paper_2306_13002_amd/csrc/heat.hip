@@ -357,14 +357,16 @@ hipError_t h2_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 }
 
 // Saturated tiles offered: (TX, TY) with TX*TY a multiple of 64, <= 1024.
-#define HEAT3D7_SAT_TILES(X) X(32, 2) X(32, 4) X(32, 8) X(32, 16) X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(128, 1) X(128, 2) \
+#define HEAT3D7_SAT_TILES(X) X(32, 2) X(32, 4) X(32, 8) X(32, 16) X(32, 20) X(32, 24) X(32, 28) X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(128, 1) X(128, 2) \
     X(128, 4) X(256, 1) X(256, 2)
 
 // Two-sweep tiles (block = TX x (TY + ring rows) <= 1024 threads); each is
 // also a single-sweep tile (an odd sweep count starts with one single sweep).
-// 32 x 16 recomputes the fewest ring cells per tile cell (1.20x) and is the
-// fastest at 160^3, 400^3 and in the 64-grid batch.
-#define HEAT3D7_SAT2_TILES(X) X(32, 4) X(32, 8) X(32, 16) X(64, 4) X(64, 8) X(128, 4)
+// Tall 32-wide tiles recompute the fewest ring cells per tile cell (1.20x at
+// 32 x 16, 1.14x at 32 x 28): 32 x 16 is the fastest at 160^3, 32 x 28 on
+// HBM-resident grids (400^3, the largest classes of the 64-grid batch).
+#define HEAT3D7_SAT2_TILES(X) X(32, 4) X(32, 8) X(32, 16) X(32, 20) X(32, 24) X(32, 28) X(64, 4) X(64, 8) \
+    X(128, 4)
 
 bool h3_tile_ok(int v, Tile t) {
     if (v == V_PLAIN) return plain_tile_ok(t);

@@ -19,7 +19,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 PLAIN_TILES = [(64, 4, 1), (64, 2, 2), (128, 2, 1), (256, 1, 1), (32, 8, 1), (64, 8, 1)]
-HEAT_SAT_TILES = [(32, 2), (32, 4), (32, 8), (32, 16), (64, 1), (64, 2), (64, 4), (64, 8), (128, 1), (128, 2), (128, 4),
+HEAT_SAT_TILES = [(32, 2), (32, 4), (32, 8), (32, 16), (32, 20), (32, 24), (32, 28), (64, 1), (64, 2), (64, 4), (64, 8), (128, 1), (128, 2), (128, 4),
                   (256, 1), (256, 2)]
 P19_SAT_TILES = [(32, 2), (32, 4), (32, 8), (64, 1), (64, 2), (64, 4), (64, 8), (128, 1), (128, 2), (128, 4), (128, 8),
                  (256, 1), (256, 4)]
@@ -107,7 +107,7 @@ def test_heat3d7_saturated(dev, tile, zb):
     assert abs(gr - wr) <= 1e-10 * wr
 
 
-H3_SAT2_TILES = [(32, 4), (32, 8), (32, 16), (64, 4), (64, 8), (128, 4)]
+H3_SAT2_TILES = [(32, 4), (32, 8), (32, 16), (32, 20), (32, 24), (32, 28), (64, 4), (64, 8), (128, 4)]
 
 
 @pytest.mark.parametrize("tile", H3_SAT2_TILES)
