@@ -286,6 +286,40 @@ __device__ __forceinline__ double p19_update(const L *m, const L *o, const L *u,
     return ss;
 }
 
+// p19_update with the plane-above and plane-below terms supplied: the centre
+// values pc, pU, pD and the z-differences B1v, B2v (each the difference of
+// a y- or x-difference of plane zc+1 and the same one of plane zc-1, kept
+// from two planes earlier instead of being read again).  The same operands
+// and operations as p19_update.
+template <int W>
+__device__ __forceinline__ double p19_update_zq(const float *o, int e, double pc, double pU, double pD, double B1v,
+                                                double B2v, const float *cc, double omega, float *out) {
+    const double pE = o[e + 1], pW = o[e - 1], pN = o[e + W], pS = o[e - W];
+    const double B0v = ((double)o[e + W + 1] - (double)o[e - W + 1]) - ((double)o[e + W - 1] - (double)o[e - W - 1]);
+    double s0 = fma((double)cc[B0], B0v, (double)cc[WRK1]);
+    s0 = fma((double)cc[B1], B1v, s0);
+    s0 = fma((double)cc[B2], B2v, s0);
+    s0 = fma((double)cc[A0], pE, s0);
+    s0 = fma((double)cc[C0], pW, s0);
+    s0 = fma((double)cc[A1], pN, s0);
+    s0 = fma((double)cc[C1], pS, s0);
+    s0 = fma((double)cc[A2], pU, s0);
+    s0 = fma((double)cc[C2], pD, s0);
+    const double ss = fma(s0, (double)cc[A3], -pc) * (double)cc[BND];
+    *out = (float)fma(omega, ss, pc);
+    return ss;
+}
+
+// The centre value and the y- and x-differences of one plane at e.
+struct ZTerms {
+    float c;
+    double dy, dx;
+};
+template <int W>
+__device__ __forceinline__ ZTerms z_terms(const float *q, int e) {
+    return ZTerms{q[e], (double)q[e + W] - (double)q[e - W], (double)q[e + 1] - (double)q[e - 1]};
+}
+
 // SATURATED, two sweeps per pass over memory (temporal blocking).  A block
 // owns a TX x TY output tile and streams z.  Sweep 1 is computed on the tile
 // plus a one-cell ring (its values are needed by sweep 2's neighbours and are
@@ -312,6 +346,11 @@ struct Sat2Shape {
     // 10-20 more VGPRs: measured 5 % faster at 64 x 8, slower at the other
     // shapes (lost occupancy, or spills at 896 threads)
     static constexpr bool UNROLL = TX == 64 && TY == 8;
+    // z-queues (each thread keeps the centre values and y-/x-differences of
+    // the two planes below the one it reads): 19 -> 13 LDS reads and
+    // conversions per update; 26 more VGPRs, which only 64 x 8 absorbs
+    // without losing occupancy (26.2 -> 25.2 us per sweep there)
+    static constexpr bool ZQ = TX == 64 && TY == 8;
 };
 
 template <int TX, int TY>
@@ -395,6 +434,16 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
             c2[s] = 0.0f;
         }
     }
+    // z-queues: the terms of planes zA-1 and zA for sweep 1 (from the p^t
+    // ring) and of planes zc-1 and zc for sweep 2 (from the sweep-1 ring)
+    ZTerms q1m{}, q1o{}, q2m{}, q2o{};
+    if constexpr (S::ZQ) {
+        __syncthreads();
+        if (has_a) {
+            q1m = z_terms<W0>(r0[3], e0_a);  // plane zlo-1 (unused when zlo = 0: sweep 1 copies plane 0)
+            q1o = z_terms<W0>(r0[0], e0_a);
+        }
+    }
     double acc = 0.0;
 
     // Iteration zA: sweep 1 at plane zA, sweep 2 at plane zA-2 (its inputs,
@@ -423,21 +472,47 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
             }
         }
         __syncthreads();
-        if (zA <= zhi && has_a) {  // sweep 1 at plane zA: own cell or ring cell
-            const bool zin = zA >= 1 && zA <= g.nz;
-            const float *m = r0[SM], *o = r0[S0], *u = r0[SP];
-            float v;
-            if (zin && in_a) p19_update<W0>(m, o, u, e0_a, cc, omega, &v);
-            else v = o[e0_a];
-            r1[S0][e1_a] = v;
-        }
         const int zc = zA - 2;  // sweep 2 at plane zc, from sweep-1 planes zc-1 .. zc+1
-        if (zc >= k0 + 1 && in_o) {
-            const float *m = r1[SP], *o = r1[S2], *u = r1[SM];
-            float v;
-            const double ss = p19_update<W1>(m, o, u, e1_o, c2, omega, &v);
-            pn[col_o + (long long)zc * g.pz] = v;
-            acc = fma(ss, ss, acc);
+        if constexpr (S::ZQ) {
+            if (zA <= zhi && has_a) {  // sweep 1 at plane zA: own cell or ring cell
+                const bool zin = zA >= 1 && zA <= g.nz;
+                const ZTerms t = z_terms<W0>(r0[SP], e0_a);  // plane zA+1
+                float v;
+                if (zin && in_a)
+                    p19_update_zq<W0>(r0[S0], e0_a, q1o.c, t.c, q1m.c, t.dy - q1m.dy, t.dx - q1m.dx, cc, omega, &v);
+                else v = q1o.c;
+                r1[S0][e1_a] = v;
+                q1m = q1o;
+                q1o = t;
+            }
+            if (zA > zlo && tile_t) {
+                const ZTerms t = z_terms<W1>(r1[SM], e1_o);  // plane zc+1
+                if (zc >= k0 + 1 && in_o) {
+                    float v;
+                    const double ss = p19_update_zq<W1>(r1[S2], e1_o, q2o.c, t.c, q2m.c, t.dy - q2m.dy,
+                                                        t.dx - q2m.dx, c2, omega, &v);
+                    pn[col_o + (long long)zc * g.pz] = v;
+                    acc = fma(ss, ss, acc);
+                }
+                q2m = q2o;
+                q2o = t;
+            }
+        } else {
+            if (zA <= zhi && has_a) {  // sweep 1 at plane zA: own cell or ring cell
+                const bool zin = zA >= 1 && zA <= g.nz;
+                const float *m = r0[SM], *o = r0[S0], *u = r0[SP];
+                float v;
+                if (zin && in_a) p19_update<W0>(m, o, u, e0_a, cc, omega, &v);
+                else v = o[e0_a];
+                r1[S0][e1_a] = v;
+            }
+            if (zc >= k0 + 1 && in_o) {
+                const float *m = r1[SP], *o = r1[S2], *u = r1[SM];
+                float v;
+                const double ss = p19_update<W1>(m, o, u, e1_o, c2, omega, &v);
+                pn[col_o + (long long)zc * g.pz] = v;
+                acc = fma(ss, ss, acc);
+            }
         }
 #pragma unroll
         for (int s = 0; s < 12; ++s) {
