@@ -156,9 +156,11 @@ __global__ __launch_bounds__(TX *TY) void heat3d7_sat(const double *__restrict__
 // by every block that needs it).  p^t planes sit in a four-plane LDS ring
 // with a two-cell halo, sweep-1 planes in a four-plane ring; sweep 2 runs two
 // planes behind sweep 1, one barrier per plane.  Each value is computed with
-// the same operations as heat3d7_sat_tile (z neighbours come from the LDS
-// ring instead of the register queue: the same numbers), so two sweeps equal
-// two launches of the single-sweep form bit for bit.  Dirichlet only.
+// the same operations as heat3d7_sat_tile, so two sweeps equal two launches
+// of the single-sweep form bit for bit.  In-plane neighbours come from the
+// LDS rings; the centre values of the planes above and below from per-thread
+// z-queues (sweep 2's from the thread's own sweep-1 values), which cuts the
+// LDS reads per output column from 14 to 9.  Dirichlet only.
 template <int TX, int TY>
 struct H3Sat2Shape {
     static constexpr int W0 = TX + 4, PL0 = (TY + 4) * W0, W1 = TX + 2, PL1 = (TY + 2) * W1;
@@ -216,6 +218,15 @@ __device__ __forceinline__ double heat3d7_sat2_tile(const double *__restrict__ s
     double ctr = ld_o ? src[col_o + (long long)(zlo + 1) * g.pz] : 0.0;
     halo.load(src + (long long)(zlo + 1) * g.pz);
     double acc = 0.0;
+    // z-queues of centre values: q1m, q1o = planes zA-1, zA of p^t at this
+    // thread's sweep-1 cell; s1a, s1b, s1c = this thread's own sweep-1 values
+    // of planes zA-1, zA-2, zA-3 (for a tile thread, the centres sweep 2 reads)
+    double q1m = 0.0, q1o = 0.0, s1a = 0.0, s1b = 0.0, s1c = 0.0;
+    __syncthreads();
+    if (has_a) {
+        q1m = r0[3][e0_a];  // plane zlo-1 (unused when zlo = 0: sweep 1 copies plane 0)
+        q1o = r0[0][e0_a];
+    }
     // ring slots relative to zlo: plane z sits in slot (z - zlo) mod 4; SM,
     // S0, SP, S2 are the slots of planes zA-1, zA, zA+1 and zA+2 (= zA-2)
     auto step = [&](const int zA, const int SM, const int S0, const int SP, const int S2) {
@@ -229,26 +240,33 @@ __device__ __forceinline__ double heat3d7_sat2_tile(const double *__restrict__ s
             }
         }
         __syncthreads();
+        double v1 = 0.0;
         if (zA <= zhi && has_a) {  // sweep 1 at plane zA
-            const double *m = r0[SM], *o = r0[S0], *u = r0[SP];
+            const double *o = r0[S0];
             const int e = e0_a;
-            double v = o[e];
+            const double uc = r0[SP][e];
+            v1 = q1o;
             if (zA >= 1 && zA <= g.nz && in_a) {
-                const double s = ((o[e - 1] + o[e + 1]) + (o[e - W0] + o[e + W0])) + (m[e] + u[e]);
-                v = fma(cn, s, cc * o[e]);
+                const double s = ((o[e - 1] + o[e + 1]) + (o[e - W0] + o[e + W0])) + (q1m + uc);
+                v1 = fma(cn, s, cc * q1o);
             }
-            r1[S0][e1_a] = v;
+            r1[S0][e1_a] = v1;
+            q1m = q1o;
+            q1o = uc;
         }
         const int zc = zA - 2;  // sweep 2 at plane zc
         if (zc >= k0 + 1 && in_o) {
-            const double *m = r1[SP], *o = r1[S2], *u = r1[SM];
+            const double *o = r1[S2];
             const int e = e1_o;
-            const double s = ((o[e - 1] + o[e + 1]) + (o[e - W1] + o[e + W1])) + (m[e] + u[e]);
-            const double v = fma(cn, s, cc * o[e]);
+            const double s = ((o[e - 1] + o[e + 1]) + (o[e - W1] + o[e + W1])) + (s1c + s1a);
+            const double v = fma(cn, s, cc * s1b);
             dst[col_o + (long long)zc * g.pz] = v;
-            const double d = v - o[e];
+            const double d = v - s1b;
             acc = fma(d, d, acc);
         }
+        s1c = s1b;
+        s1b = s1a;
+        s1a = v1;
     };
     // four planes per trip, so that every slot is a compile-time constant
     // (7-10 % faster than slots computed per plane)
