@@ -538,6 +538,9 @@ def main():
         },
         "residual": main_r["resid"],
     }
+    if "classes" in main_r["cfg"]:  # batched plans: one form and launch shape per size class
+        out["config"]["classes"] = [{"variant": c["variant"], "tile": list(c["tile"]), "problems": c["problems"]}
+                                    for c in main_r["cfg"]["classes"]]
     if per_launch > 1 and roof["bound"] == "hbm":
         # a launch advances per_launch sweeps for one pass of bytes: the rate a
         # single-sweep kernel would need to match it (may exceed the peak)

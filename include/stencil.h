@@ -163,9 +163,13 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out);
 /* Build one plan over `count` independent grids (HEAT3D7, Dirichlet), run
  * together: problems are grouped into size classes by their largest
  * interior edge (<= 64, then buckets of 32); each class gets one form and
- * launch shape -- from the autotuner on the class's largest problem when
- * ds[0].tune is EXHAUSTIVE, else the defaults or ds[0]'s fields -- and a
- * persistent work-list kernel over (problem, tile) items.  stencil_run on a
+ * launch shape -- when ds[0].tune is not FIXED and ds[0] leaves the form or
+ * shape open, by timing the class's own work-list kernel over all its
+ * problems (on scratch grids the library allocates for the tuning and frees;
+ * on E_NOMEM for those, by tuning its largest problem alone), else the
+ * defaults or ds[0]'s fields -- and a persistent work-list kernel over
+ * (problem, tile) items.  stencil_batch_problem_config reports each
+ * problem's class and shape.  stencil_run on a
  * batch plan takes fields = {p0.fields[0], p0.fields[1], p1.fields[0], ...}
  * and replays one hipGraph per (iterations, field pointers): halo copies, the
  * class chains as parallel branches, tail copies.  Each problem's result is
@@ -208,6 +212,14 @@ stencil_status stencil_residuals(stencil_plan_t p, double *host_out, int32_t cou
  * tile_map is reported as 1 (natural) or 2 (XCD-chunked). */
 stencil_status stencil_plan_config(stencil_plan_t p, int32_t *variant, int32_t *tile_x, int32_t *tile_y,
                                    int32_t *zblock, int32_t *tile_map);
+
+/* Size class and launch configuration of problem `problem` (0-based, in the
+ * order given to stencil_plan_batch) of a batch plan; any output pointer may
+ * be NULL.  size_class numbers the plan's non-empty classes from the
+ * smallest edge bucket up; variant, tile and z-block are that class's.
+ * E_INVAL if p is not a batch plan or problem is out of range. */
+stencil_status stencil_batch_problem_config(stencil_plan_t p, int32_t problem, int32_t *size_class, int32_t *variant,
+                                            int32_t *tile_x, int32_t *tile_y, int32_t *zblock);
 
 /* Graph replay of repeated runs for a single plan (off by default; GENERIC
  * and batched plans: E_UNSUPPORTED, batches always run as graphs).  One

@@ -633,6 +633,21 @@ stencil_status stencil_plan_config(stencil_plan_t p, int32_t *variant, int32_t *
     return STENCIL_OK;
 }
 
+stencil_status stencil_batch_problem_config(stencil_plan_t p, int32_t problem, int32_t *size_class, int32_t *variant,
+                                            int32_t *tile_x, int32_t *tile_y, int32_t *zblock) {
+    if (!p || !p->batch) return fail(STENCIL_E_INVAL, "not a batch plan");
+    const BatchState *b = p->batch;
+    if (problem < 0 || problem >= b->count) return fail(STENCIL_E_INVAL, "problem %d of %d", problem, b->count);
+    const int c = b->prob_class[problem];
+    const BatchClass &C = b->classes[c];
+    if (size_class) *size_class = c;
+    if (variant) *variant = C.variant;
+    if (tile_x) *tile_x = C.tile.tx;
+    if (tile_y) *tile_y = C.tile.ty;
+    if (zblock) *zblock = C.tile.tz;
+    return STENCIL_OK;
+}
+
 stencil_status stencil_plan_use_graphs(stencil_plan_t p, int32_t enable) {
     if (!p) return fail(STENCIL_E_INVAL, "plan is NULL");
     if (p->batch) return fail(STENCIL_E_UNSUPPORTED, "batched plans always run as graphs");

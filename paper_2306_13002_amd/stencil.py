@@ -72,6 +72,7 @@ def lib():
         L.stencil_residual.argtypes = [vp, dp, vp]
         L.stencil_plan_config.argtypes = [vp] + [ctypes.POINTER(i32)] * 5
         L.stencil_plan_graph.argtypes = [vp, ctypes.POINTER(i32)]
+        L.stencil_batch_problem_config.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 5
         L.stencil_plan_use_graphs.argtypes = [vp, i32]
         L.stencil_profile_enable.argtypes = [vp, i32]
         L.stencil_profile_read.argtypes = [vp, dp, ctypes.POINTER(i32)]
@@ -86,7 +87,7 @@ def lib():
         L.stencil_prepare.argtypes = [ctypes.POINTER(StencilDesc)]
         L.stencil_prepare.restype = ctypes.c_int
         for f in (L.stencil_plan, L.stencil_run, L.stencil_residual, L.stencil_plan_config, L.stencil_plan_graph,
-                  L.stencil_plan_use_graphs,
+                  L.stencil_plan_use_graphs, L.stencil_batch_problem_config,
                   L.stencil_profile_enable, L.stencil_profile_read, L.stencil_destroy, L.stencil_plan_batch,
                   L.stencil_residuals, L.stencil_candidates, L.stencil_features, L.stencil_mlp_train,
                   L.stencil_mlp_predict):
@@ -313,11 +314,30 @@ class BatchPlan:
         _check(lib().stencil_run(self._h, fp, None, int(iterations), ctypes.c_void_p(_stream_handle(stream))))
 
     def config(self) -> dict:
-        """Form and launch shape of the first size class."""
+        """Form and launch shape of the first size class, and every class's
+        (form, launch shape, number of problems) under "classes"."""
         v, tx, ty, zb, m = (ctypes.c_int32() for _ in range(5))
         _check(lib().stencil_plan_config(self._h, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(zb),
                                          ctypes.byref(m)))
-        return {"variant": VARIANT_NAMES[v.value], "tile": (tx.value, ty.value, zb.value), "tile_map": "batch"}
+        classes = [{"variant": c["variant"], "tile": c["tile"], "problems": len(c["problems"])} for c in self.classes()]
+        return {"variant": VARIANT_NAMES[v.value], "tile": (tx.value, ty.value, zb.value), "tile_map": "batch",
+                "classes": classes}
+
+    def problem_config(self, i: int) -> dict:
+        """Size class, form and launch shape of problem i."""
+        c, v, tx, ty, zb = (ctypes.c_int32() for _ in range(5))
+        _check(lib().stencil_batch_problem_config(self._h, int(i), ctypes.byref(c), ctypes.byref(v), ctypes.byref(tx),
+                                                  ctypes.byref(ty), ctypes.byref(zb)))
+        return {"size_class": c.value, "variant": VARIANT_NAMES[v.value], "tile": (tx.value, ty.value, zb.value)}
+
+    def classes(self) -> list:
+        """One entry per size class: its form, launch shape and problem indices."""
+        out = {}
+        for i in range(len(self.n)):
+            pc = self.problem_config(i)
+            e = out.setdefault(pc["size_class"], {"variant": pc["variant"], "tile": pc["tile"], "problems": []})
+            e["problems"].append(i)
+        return [out[k] for k in sorted(out)]
 
     def residuals(self, stream=None):
         out = (ctypes.c_double * len(self.n))()

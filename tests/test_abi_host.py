@@ -82,6 +82,9 @@ def test_null_arguments():
     out = ctypes.c_double()
     assert L.stencil_residual(None, ctypes.byref(out), None) == S.E_INVAL
     assert L.stencil_destroy(None) == S.OK
+    c = ctypes.c_int32()
+    assert L.stencil_batch_problem_config(None, 0, ctypes.byref(c), None, None, None, None) == S.E_INVAL
+    assert "batch" in S.last_error()
     assert isinstance(S.last_error(), str)
     assert L.stencil_version().decode().endswith("gfx950")
 

@@ -125,12 +125,24 @@ def test_batch_tuned_workload(dev):
 def test_batch_two_sweep_tuned_workload(dev):
     """The 64-problem workload with two-sweep classes tuned in place (the
     benchmark's configuration), against 64 separate plain runs."""
-    from paper_2306_13002_amd.stencil import BatchPlan
+    from paper_2306_13002_amd.stencil import BatchPlan, StencilError
     sizes = synth.heat3d7_batch_sizes()
     us, fs = fields_for(sizes, dev, stream0=1)
     bp = BatchPlan(sizes, tune="exhaustive", variant="saturated_t2")
     bp.run(fs, iterations=50)
     res = bp.residuals()
+    # classes: edge buckets (<= 64, then 32 wide), numbered from the smallest,
+    # each problem in exactly one, every class with a two-sweep launch shape
+    classes = bp.classes()
+    bucket = lambda n: 0 if max(n) <= 64 else (max(n) - 65) // 32 + 1
+    assert sorted(i for c in classes for i in c["problems"]) == list(range(len(sizes)))
+    keys = [bucket(sizes[c["problems"][0]]) for c in classes]
+    assert keys == sorted(set(keys))
+    for c in classes:
+        assert {bucket(sizes[i]) for i in c["problems"]} == {bucket(sizes[c["problems"][0]])}
+        assert c["variant"] == "saturated_t2" and min(c["tile"]) >= 1
+    with pytest.raises(StencilError, match="problem"):
+        bp.problem_config(len(sizes))
     bp.close()
     for i, n in enumerate(sizes):
         want, wr = single(n, us[i], 50, dev, variant="plain")
