@@ -278,8 +278,46 @@ def time_variant(name, variant, steps, warmup, dev, torch, synth, Plan, plan_kw=
                 sweep_ms_median=per_step[len(per_step) // 2], sweep_ms_best=per_step[0])
 
 
+def cpu_threads():
+    """Host threads for the all-cores oracle run: the cores this process may
+    use, at most 16 (one GPU's share of a host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def all_cores(call, pts_per_call, one_s, label):
+    """The same oracle call run by one thread per core at once (the oracle's
+    C body runs without the GIL), each on its own copy of the inputs, for
+    about 10 s; returns the aggregate rate."""
+    import threading
+
+    n = cpu_threads()
+    reps = max(1, int(10.0 / max(one_s, 1e-3)))
+    barrier = threading.Barrier(n + 1)
+
+    def work():
+        barrier.wait()
+        for _ in range(reps):
+            call()
+
+    ts = [threading.Thread(target=work) for _ in range(n)]
+    for t in ts:
+        t.start()
+    barrier.wait()
+    t0 = time.perf_counter()
+    for t in ts:
+        t.join()
+    dt = time.perf_counter() - t0
+    return dict(value=n * reps * pts_per_call / dt, cores=n,
+                sample=f"{n} threads, each {reps} x ({label}), {dt:.1f} s")
+
+
 def cpu_baseline(name):
-    """Time the CPU oracle (single thread, as written) on a bounded sample."""
+    """Time the CPU oracle (single thread, as written) on a bounded sample,
+    and the same calls on every core at once ("all_cores")."""
     import numpy as np
 
     import oracle
@@ -296,8 +334,11 @@ def cpu_baseline(name):
         oracle.poisson19(p0, cf, 0.8, k, mode="F32STORE")
         dt = time.perf_counter() - t
         pts = 127 * 127 * 255 * k
+        ac = all_cores(lambda: oracle.poisson19(p0, cf, 0.8, 8, mode="F32STORE"), 127 * 127 * 255 * 8, 8 * one,
+                       "8 sweeps of the full grid")
         return dict(value=pts / dt, unit="grid-point updates/s", cores=1, kind="oracle",
-                    sample=f"full 129x129x257 grid, {k} sweeps (F32STORE mode), {dt:.1f} s, single thread")
+                    sample=f"full 129x129x257 grid, {k} sweeps (F32STORE mode), {dt:.1f} s, single thread",
+                    all_cores=ac)
     if name == "wave25":
         a, b, v = synth.wave25_inputs(128, 128, 128)
         t = time.perf_counter()
@@ -307,8 +348,10 @@ def cpu_baseline(name):
         t = time.perf_counter()
         oracle.wave25(a, b, v, synth.WAVE25_COEF, k)
         dt = time.perf_counter() - t
+        ac = all_cores(lambda: oracle.wave25(a, b, v, synth.WAVE25_COEF, 2), 128 ** 3 * 2, 2 * one,
+                       "2 steps of the 128^3 crop")
         return dict(value=128 ** 3 * k / dt, unit="grid-point updates/s", cores=1, kind="oracle",
-                    sample=f"128^3 crop of the same recipe, {k} steps, {dt:.1f} s, single thread")
+                    sample=f"128^3 crop of the same recipe, {k} steps, {dt:.1f} s, single thread", all_cores=ac)
     if name == "generic":
         w = synth.generic_box_workload()
         n = (64, 64, 64)
@@ -320,8 +363,10 @@ def cpu_baseline(name):
         t = time.perf_counter()
         oracle.generic(u0, w["radius"], w["taps"], w["cids"], w["coef"], k)
         dt = time.perf_counter() - t
+        ac = all_cores(lambda: oracle.generic(u0, w["radius"], w["taps"], w["cids"], w["coef"], 1), 64 ** 3, one,
+                       "1 sweep of the 64^3 crop")
         return dict(value=64 ** 3 * k / dt, unit="grid-point updates/s", cores=1, kind="oracle",
-                    sample=f"64^3 crop of the same recipe, {k} sweeps, {dt:.1f} s, single thread")
+                    sample=f"64^3 crop of the same recipe, {k} sweeps, {dt:.1f} s, single thread", all_cores=ac)
     u0 = synth.heat3d7_input(96, 96, 96) if name == "heat3d7" else synth.heat2d5_input(256)
     cc = 0.4 if name == "heat3d7" else 0.6
     t = time.perf_counter()
@@ -332,8 +377,10 @@ def cpu_baseline(name):
     oracle.heat(u0, k, cc, 0.1)
     dt = time.perf_counter() - t
     pts = int(np.prod([s - 2 for s in u0.shape])) * k
+    ac = all_cores(lambda: oracle.heat(u0, 20, cc, 0.1), int(np.prod([s - 2 for s in u0.shape])) * 20, one,
+                   f"20 sweeps of the {u0.shape} padded grid")
     return dict(value=pts / dt, unit="grid-point updates/s", cores=1, kind="oracle",
-                sample=f"{u0.shape} padded grid, {k} sweeps, {dt:.1f} s, single thread")
+                sample=f"{u0.shape} padded grid, {k} sweeps, {dt:.1f} s, single thread", all_cores=ac)
 
 
 LHS_TILES = [(64, 4), (128, 2), (256, 1), (64, 8), (128, 4), (256, 2)]
