@@ -384,6 +384,54 @@ def cpu_baseline(name):
 
 
 LHS_TILES = [(64, 4), (128, 2), (256, 1), (64, 8), (128, 4), (256, 2)]
+PROGRAM_FORMS = ("plain", "cse", "cse_sat", "cse_bulk", "accsat", "accsat_z")
+
+
+def program_ablation(torch, prog, n, host_ins, params, bytes_per_pt, reps=20):
+    """A loop body through the saturator in the paper's ablation forms (and
+    the z-streaming form): microseconds per out-of-place pass at each form's
+    best launch shape (chosen first, from 5 timed passes per shape), then
+    the mean of `reps` passes."""
+    import concurrent.futures as cf
+
+    from paper_2306_13002_amd import saturator as X
+
+    ins = [torch.tensor(v, device="cuda") for v in host_ins]
+    outs = [torch.zeros_like(ins[0]) for _ in range(prog["n_outputs"])]
+    pts = n[0] * n[1] * n[2]
+    tiles = [(64, 4), (128, 2), (256, 1), (32, 8), (64, 8)]
+    shapes = {f: [(t[0], t[1], zb) for t in tiles for zb in ((16, 64, n[2]) if f == "accsat_z" else (1,))]
+              for f in PROGRAM_FORMS}
+    with cf.ThreadPoolExecutor(16) as ex:  # hipRTC compiles run in parallel
+        plans = dict(ex.map(lambda ft: (ft, X.ProgramPlan(prog, n, ft[0], tile=ft[1][:2], zblock=ft[1][2])),
+                            [(f, t) for f in PROGRAM_FORMS for t in shapes[f]]))
+
+    def time_plan(pl, k):
+        pl.profile(True)
+        ms = []
+        for _ in range(k):
+            pl.run(ins, outs, params)
+            ms.append(pl.profile_read())
+        return ms
+
+    res = {}
+    try:
+        for f in PROGRAM_FORMS:
+            best = None
+            for t in shapes[f]:
+                time_plan(plans[(f, t)], 1)
+                us = 1e3 * min(time_plan(plans[(f, t)], 5))
+                if best is None or us < best[1]:
+                    best = (t, us)
+            ms = time_plan(plans[(f, best[0])], reps)
+            us = 1e3 * sum(ms) / len(ms)
+            st = X.generate(prog, n, f)[2]
+            res[f] = {"us_per_sweep": us, "algorithmic_gbs": bytes_per_pt * pts / (us * 1e-6) / 1e9,
+                      "tile": list(best[0]), "loads": st["loads"], "ops": st["ops"], "fmas": st["fmas"]}
+    finally:
+        for pl in plans.values():
+            pl.close()
+    return res
 
 
 def bench_lhs(a, torch):
@@ -616,6 +664,17 @@ def main():
                 abl[form] = {"us_per_sweep": fr["sweep_ms"] / 1000.0 / max(1, fr["sweeps"]) * 1e6}
             for v in abl.values():
                 v["algorithmic_gbs"] = meta["bytes_per_update"] * pts_per_sweep / (v["us_per_sweep"] * 1e-6) / 1e9
+            out["ablation"] = abl
+        if a.workload == "heat3d7":
+            # the loop body through the saturator (generated kernels, one pass per launch) in the paper's
+            # ablation forms, beside the hand-written kernels' single-sweep forms
+            n3 = tuple(meta["interior"])
+            abl = program_ablation(torch, synth.heat3d7_program(), n3, [synth.heat3d7_input(*n3)], [0.4, 0.1],
+                                   meta["bytes_per_update"])
+            abl["kernel_plain"] = {"us_per_sweep": pl * 1e6}
+            if "saturated" in sat:
+                abl["kernel_saturated"] = {"us_per_sweep": sat["saturated"]["sweep_ms"] * 1e3 /
+                                           max(1, sat["saturated"]["sweeps"])}
             out["ablation"] = abl
     if not a.no_cpu and a.workload not in ("copy", "batch"):
         out["cpu_baseline"] = cpu_baseline(a.workload)

@@ -292,6 +292,18 @@ LHS_PARAMS = (0.5, 1.0, 4.0, 0.1, 0.2, 0.3, 0.4, 0.5)  # dt, tz1, tz2, dz[0..4]
 LHS_N = (162, 162, 162)
 
 
+# The heat3d7 loop body as a program, written as the plain kernel reads it:
+# u' = cc*u + cn*u(-x) + cn*u(+x) + cn*u(-y) + cn*u(+y) + cn*u(-z) + cn*u(+z),
+# added left to right; params cc, cn; one input, one output.
+def heat3d7_program():
+    op = lambda o: (o, 0, 0, 0, 0)  # noqa: E731
+    ins = [(_PARAM, 0, 0, 0, 0), (_LOAD, 0, 0, 0, 0), op(_MUL)]
+    for d in ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)):
+        ins += [(_PARAM, 1, 0, 0, 0), (_LOAD, 0) + d, op(_MUL), op(_ADD)]
+    ins.append((_STORE, 0, 0, 0, 0))
+    return dict(n_inputs=1, n_outputs=1, n_params=2, n_locals=0, radius=1, insns=ins, consts=[])
+
+
 def lhs_program():
     ins = [(_PARAM, 0, 0, 0, 0), (_PARAM, 1, 0, 0, 0), (_MUL, 0, 0, 0, 0), (_SET, 0, 0, 0, 0),
            (_PARAM, 0, 0, 0, 0), (_PARAM, 2, 0, 0, 0), (_MUL, 0, 0, 0, 0), (_SET, 1, 0, 0, 0)]

@@ -62,6 +62,19 @@ def test_lhs_assembly_ragged_grid(form):
     check(form, got, want, 1)
 
 
+@pytest.mark.parametrize("form", FORMS)
+def test_heat3d7_program_forms(form):
+    """The heat3d7 loop body through the saturator in every form of the
+    paper's ablation, against the oracle's heat sweep (the same arithmetic
+    as the program for the forms without rules)."""
+    n = (37, 13, 11)
+    print(f"heat3d7 program {form}", flush=True)
+    u0 = synth.heat3d7_input(*n, stream=12)
+    want, _ = oracle.heat(u0, 1, 0.4, 0.1)
+    got = run(synth.heat3d7_program(), n, [dev(u0)], [0.4, 0.1], form, zblock=4 if form == "accsat_z" else 0)
+    check(form, got, [want], 1)
+
+
 @pytest.mark.parametrize("idx", range(8))
 @pytest.mark.parametrize("form", FORMS)
 def test_random_programs(idx, form):

@@ -113,6 +113,21 @@ def test_lhs_depends_on_the_neighbour_planes():
     assert all(d == [] for o, d in enumerate(diff) if o not in (0, 50))
 
 
+def test_heat3d7_program_is_the_heat_sweep():
+    """The heat3d7 loop body written as a program, run by the interpreter,
+    gives the oracle's heat sweep bit for bit (same operations, same order),
+    and leaves the halo at zero."""
+    prog = synth.heat3d7_program()
+    n = (9, 7, 5)
+    u0 = synth.heat3d7_input(*n, stream=3)
+    got = oracle.program(prog, [u0], [0.4, 0.1], n)[0]
+    want, _ = oracle.heat(u0, 1, 0.4, 0.1)
+    assert np.array_equal(got[1:-1, 1:-1, 1:-1], want[1:-1, 1:-1, 1:-1])
+    h = got.copy()
+    h[1:-1, 1:-1, 1:-1] = 0.0
+    assert not np.any(h)
+
+
 def test_malformed_program_rejected_by_the_oracle():
     bad = dict(n_inputs=1, n_outputs=1, n_params=0, n_locals=0, radius=1, insns=[(4, 0, 0, 0, 0), (8, 0, 0, 0, 0)],
                consts=[])
