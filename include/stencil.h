@@ -79,7 +79,10 @@ typedef enum {
  *             L(u) = sum over x,y,z of [c0*u + sum_{q=1..4} c_q*(u(+q) + u(-q))]
  *             u_next = 2u - u_prev + vsq*L(u);   coef = {c0,c1,c2,c3,c4}.
  * GENERIC   u'(x) = sum_t coef[cid_t] * u(x + delta_t), 3-D, radius 1..4,
- *           F32 or F64, taps given by tap_off/tap_cid.
+ *           F32 or F64, taps given by tap_off/tap_cid.  Its saturated
+ *           kernels are generated and launched through the module API,
+ *           which limits them to ny, nz <= 65535 (E_UNSUPPORTED above;
+ *           PLAIN takes every extent up to 2^24).
  */
 typedef enum {
     STENCIL_HEAT2D5 = 1,

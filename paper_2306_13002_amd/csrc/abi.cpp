@@ -236,6 +236,10 @@ stencil_status validate_desc(const stencil_desc *d, Geom &g, int &rz) {
         if (!d->coef || d->n_coef < 1) return fail(STENCIL_E_INVAL, "GENERIC needs n_coef >= 1 coefficients");
         if (d->n_taps < 1 || d->n_taps > 729 || !d->tap_off || !d->tap_cid)
             return fail(STENCIL_E_INVAL, "GENERIC needs 1..729 taps with tap_off and tap_cid");
+        // the generated saturated kernels go through hipModuleLaunchKernel,
+        // which refuses y or z grid dimensions above 65535 blocks
+        if (d->variant != STENCIL_PLAIN && (d->n[1] > 65535 || d->n[2] > 65535))
+            return fail(STENCIL_E_UNSUPPORTED, "GENERIC saturated kernels need ny, nz <= 65535 (PLAIN takes any extent)");
         for (int t = 0; t < d->n_taps; ++t) {
             for (int a = 0; a < 3; ++a)
                 if (d->tap_off[3 * t + a] < -r || d->tap_off[3 * t + a] > r)

@@ -70,6 +70,8 @@ stencil_status check_shape(const sat::Program &p, int form, int *tx, int *ty, in
     if (*tx < 1 || *ty < 1 || nt % 64 != 0 || nt > 1024)
         return fail(STENCIL_E_INVAL, "block %d x %d: threads must be a multiple of 64, at most 1024", *tx, *ty);
     if ((p.n[1] + *ty - 1) / *ty > 65535 || (p.n[2] + *zb - 1) / *zb > 65535)
+        // generated kernels go through hipModuleLaunchKernel, which refuses y or
+        // z grid dimensions above 65535 (the runtime launch path takes more)
         return fail(STENCIL_E_UNSUPPORTED, "grid too large for one launch (y blocks and z extent must be <= 65535)");
     return STENCIL_OK;
 }

@@ -72,6 +72,20 @@ def test_bad_descriptors_rejected_on_host(kw, status, msg):
     assert msg in S.last_error()
 
 
+def test_generated_kernels_refuse_grids_the_module_launch_cannot_take():
+    """Saturated GENERIC kernels and generated programs are launched through
+    hipModuleLaunchKernel (y and z grid dimensions up to 65535): taller
+    grids are refused on the host, before any device call."""
+    L = S.lib()
+    taps = [(0, 0, 0), (1, 0, 0), (0, 0, -1)]
+    for variant, status in (("saturated", S.E_UNSUPPORTED), ("auto", S.E_UNSUPPORTED)):
+        d, keep = S.make_desc("generic", (4, 4, 70000), dtype="f64", radius=1, coef=(0.5, 0.25), taps=taps,
+                              cids=[0, 1, 1], variant=variant)
+        h = ctypes.c_void_p()
+        assert L.stencil_plan(ctypes.byref(d), ctypes.byref(h)) == status
+        assert "65535" in S.last_error()
+
+
 def test_null_arguments():
     L = S.lib()
     h = ctypes.c_void_p()

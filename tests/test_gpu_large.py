@@ -158,3 +158,32 @@ def test_wave25_beyond_2_31_elements(dev, variant):
         err = maxrel(host(f[0], gsl), compare_region(A, off, 4))
         assert err <= (0 if variant == "plain" else 1e-12), (lo, err)
     assert torch.equal(f[0][-4:], a[-4:]) and torch.equal(f[0][:, :, :4], a[:, :, :4])
+
+
+@pytest.mark.parametrize("variant", ["plain", "saturated", "saturated_t2"])
+def test_tall_grids_beyond_65535_planes(dev, variant):
+    """Thin columns taller than 65 535 planes: the plain kernels launch one
+    block row per plane (a z grid dimension above 65 535), the saturated
+    forms block z; every form against the oracle on the whole grid."""
+    from paper_2306_13002_amd.stencil import Plan
+    n, T = (3, 2, 70001), 3
+    print(f"tall heat3d7 {variant} n={n}", flush=True)
+    u0 = synth.heat3d7_input(*n, stream=44)
+    p = Plan("heat3d7", n, variant=variant, coef=(0.4, 0.1), tune="fixed")
+    f = [torch.tensor(u0, device=dev), torch.full(u0.shape, float("nan"), dtype=torch.float64, device=dev)]
+    p.run(f, iterations=T)
+    gr = p.residual()
+    p.close()
+    want, wr = oracle.heat(u0, T, 0.4, 0.1)
+    got = f[0].cpu().numpy()
+    assert maxrel(got[1:-1, 1:-1, 1:-1], want[1:-1, 1:-1, 1:-1]) <= (0 if variant == "plain" else 1e-12)
+    assert abs(gr - wr) <= 1e-10 * wr
+    print(f"tall poisson19 {variant} n={n}", flush=True)
+    pp, cf = synth.poisson19_random_inputs((n[2] + 2, n[1] + 2, n[0] + 2), seed=44)
+    p = Plan("poisson19", n, variant=variant, omega=0.8, tune="fixed")
+    f = [torch.tensor(pp, device=dev), torch.zeros(pp.shape, dtype=torch.float32, device=dev)]
+    p.run(f, [torch.tensor(c, device=dev) for c in cf], iterations=T)
+    p.close()
+    w64, _ = oracle.poisson19(pp, cf, 0.8, T, mode="F64")
+    assert maxrel(f[0].cpu().numpy().astype(np.float64)[1:-1, 1:-1, 1:-1], w64[1:-1, 1:-1, 1:-1]) <= 1e-5
+

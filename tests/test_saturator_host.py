@@ -392,6 +392,9 @@ def test_bad_shapes_rejected():
         X.generate(prog, (8, 0, 8), "cse")
     with pytest.raises(S.StencilError, match="pitch_y"):
         X.generate(prog, (8, 8, 8), "cse", pitch=(9, 0))
+    # the module launch API takes at most 65535 blocks in y and z
+    with pytest.raises(S.StencilError, match="65535"):
+        X.generate(prog, (4, 4, 70000), "cse")
 
 
 def _stencil_program(taps, cids, coef, grouped):
