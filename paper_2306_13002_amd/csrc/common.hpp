@@ -97,8 +97,9 @@ __device__ __forceinline__ void tile_coords(int remap, int &bx, int &by, int &bz
 // (star stencils never read them).  Each thread keeps at most HR cells: their
 // LDS index, in-plane global offset and validity are computed once; load()
 // issues the global loads of one plane into registers (early, one plane
-// ahead) and store() writes them into LDS.
-template <typename T, int TX, int TY, int R, bool CORNERS, int NT>
+// ahead) and store() writes them into LDS.  LW: the LDS row stride (the
+// tile width unless the caller pads its rows).
+template <typename T, int TX, int TY, int R, bool CORNERS, int NT, int LW = TX + 2 * R>
 struct HaloStager {
     static constexpr int W = TX + 2 * R;
     static constexpr int BW = CORNERS ? W : TX;
@@ -140,7 +141,7 @@ struct HaloStager {
                 }
                 const int gx = x0p - R + lx, gy = y0p - R + ly;
                 ok[s] = gx >= 0 && gx < PX && gy >= 0 && gy < PY;
-                lidx[s] = ly * W + lx;
+                lidx[s] = ly * LW + lx;
                 goff[s] = (long long)gy * py + gx;
             }
         }

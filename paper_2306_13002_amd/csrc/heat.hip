@@ -163,7 +163,11 @@ __global__ __launch_bounds__(TX *TY) void heat3d7_sat(const double *__restrict__
 // LDS reads per output column from 14 to 9.  Dirichlet only.
 template <int TX, int TY>
 struct H3Sat2Shape {
-    static constexpr int W0 = TX + 4, PL0 = (TY + 4) * W0, W1 = TX + 2, PL1 = (TY + 2) * W1;
+    // W0, W1: widths of the p^t and sweep-1 tiles; LS0, LS1: their LDS row
+    // strides, odd numbers of doubles so that the ring threads' column
+    // accesses spread over the banks
+    static constexpr int W0 = TX + 4, LS0 = W0 + 1, PL0 = (TY + 4) * LS0;
+    static constexpr int W1 = TX + 2, LS1 = W1 + 1, PL1 = (TY + 2) * LS1;
     static constexpr int RS = 2 * W1 + 2 * TY;
     static constexpr int EY0 = (RS + TX - 1) / TX;
     static constexpr int EY = (TX * (TY + EY0)) % 64 == 0 ? EY0 : EY0 + 1;
@@ -176,7 +180,7 @@ __device__ __forceinline__ double heat3d7_sat2_tile(const double *__restrict__ s
                                                     int bz, double (*r0)[H3Sat2Shape<TX, TY>::PL0],
                                                     double (*r1)[H3Sat2Shape<TX, TY>::PL1]) {
     using S = H3Sat2Shape<TX, TY>;
-    constexpr int W0 = S::W0, W1 = S::W1, NT = S::NT, RS = S::RS;
+    constexpr int W1 = S::W1, LS0 = S::LS0, LS1 = S::LS1, NT = S::NT, RS = S::RS;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const int PX = g.nx + 2, PY = g.ny + 2;
     const int k0 = bz * zb, k1 = min(k0 + zb, g.nz);
@@ -185,7 +189,7 @@ __device__ __forceinline__ double heat3d7_sat2_tile(const double *__restrict__ s
     const bool in_o = tile_t && xo <= g.nx && yo <= g.ny;
     const bool ld_o = tile_t && xo < PX && yo < PY;
     const long long col_o = (long long)yo * g.py + xo;
-    const int e0_o = (ty + 2) * W0 + tx + 2, e1_o = (ty + 1) * W1 + tx + 1;
+    const int e0_o = (ty + 2) * LS0 + tx + 2, e1_o = (ty + 1) * LS1 + tx + 1;
     const int q = tid - TX * TY;
     const bool has_r = !tile_t && q < RS;
     int ex = 0, ey = 0;
@@ -203,9 +207,9 @@ __device__ __forceinline__ double heat3d7_sat2_tile(const double *__restrict__ s
     const int xr = bx * TX + ex, yr = by * TY + ey;
     const bool in_r = has_r && xr >= 1 && xr <= g.nx && yr >= 1 && yr <= g.ny;
     const bool in_a = tile_t ? in_o : in_r, has_a = tile_t || has_r;
-    const int e0_a = tile_t ? e0_o : (ey + 1) * W0 + ex + 1, e1_a = tile_t ? e1_o : ey * W1 + ex;
+    const int e0_a = tile_t ? e0_o : (ey + 1) * LS0 + ex + 1, e1_a = tile_t ? e1_o : ey * LS1 + ex;
 
-    HaloStager<double, TX, TY, 2, true, NT> halo;
+    HaloStager<double, TX, TY, 2, true, NT, LS0> halo;
     halo.init(tid, bx * TX + 1, by * TY + 1, g.py, PX, PY);
     const int zlo = k0, zhi = k1 + 1;
     for (int z = zlo - 1; z <= zlo; ++z) {
@@ -247,7 +251,7 @@ __device__ __forceinline__ double heat3d7_sat2_tile(const double *__restrict__ s
             const double uc = r0[SP][e];
             v1 = q1o;
             if (zA >= 1 && zA <= g.nz && in_a) {
-                const double s = ((o[e - 1] + o[e + 1]) + (o[e - W0] + o[e + W0])) + (q1m + uc);
+                const double s = ((o[e - 1] + o[e + 1]) + (o[e - LS0] + o[e + LS0])) + (q1m + uc);
                 v1 = fma(cn, s, cc * q1o);
             }
             r1[S0][e1_a] = v1;
@@ -258,7 +262,7 @@ __device__ __forceinline__ double heat3d7_sat2_tile(const double *__restrict__ s
         if (zc >= k0 + 1 && in_o) {
             const double *o = r1[S2];
             const int e = e1_o;
-            const double s = ((o[e - 1] + o[e + 1]) + (o[e - W1] + o[e + W1])) + (s1c + s1a);
+            const double s = ((o[e - 1] + o[e + 1]) + (o[e - LS1] + o[e + LS1])) + (s1c + s1a);
             const double v = fma(cn, s, cc * s1b);
             dst[col_o + (long long)zc * g.pz] = v;
             const double d = v - s1b;
