@@ -451,6 +451,10 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
     // barrier per plane separates every LDS write from its readers.  Ring
     // slots are relative to zlo: plane z sits in slot (z - zlo) mod 4; SM,
     // S0, SP, S2 are the slots of planes zA-1, zA, zA+1 and zA+2 (= zA-2).
+    // running plane offsets (one 64-bit add per plane instead of a multiply per access)
+    const float *pl_next = p + (long long)(zlo + 2) * g.pz;
+    long long qz = (long long)(zlo + 1) * g.pz;   // plane zA+1, the coefficients loaded at step zA
+    float *out_pl = pn + (long long)(zlo - 2) * g.pz;  // plane zc = zA-2
     auto step = [&](const int zA, const int SM, const int S0, const int SP, const int S2) {
         float cc[12];
 #pragma unroll
@@ -461,12 +465,11 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
             halo.store(r0[SP]);
             if (zA < zhi) {
                 if (zA + 2 <= g.nz + 1) {
-                    const float *pl = p + (long long)(zA + 2) * g.pz;
-                    ctr = ld_o ? pl[col_o] : 0.0f;
-                    halo.load(pl);
+                    ctr = ld_o ? pl_next[col_o] : 0.0f;
+                    halo.load(pl_next);
                 }
                 const bool zin = zA + 1 >= 1 && zA + 1 <= g.nz;
-                const long long qa = col_a + (long long)(zA + 1) * g.pz;
+                const long long qa = col_a + qz;
 #pragma unroll
                 for (int s = 0; s < 12; ++s) cf[s] = (zin && in_a) ? c.f[s][qa] : 0.0f;
             }
@@ -491,7 +494,7 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
                     float v;
                     const double ss = p19_update_zq<W1>(r1[S2], e1_o, q2o.c, t.c, q2m.c, t.dy - q2m.dy,
                                                         t.dx - q2m.dx, c2, omega, &v);
-                    pn[col_o + (long long)zc * g.pz] = v;
+                    out_pl[col_o] = v;
                     acc = fma(ss, ss, acc);
                 }
                 q2m = q2o;
@@ -510,7 +513,7 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
                 const float *m = r1[SP], *o = r1[S2], *u = r1[SM];
                 float v;
                 const double ss = p19_update<W1>(m, o, u, e1_o, c2, omega, &v);
-                pn[col_o + (long long)zc * g.pz] = v;
+                out_pl[col_o] = v;
                 acc = fma(ss, ss, acc);
             }
         }
@@ -519,6 +522,9 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
             c2[s] = c1[s];
             c1[s] = cc[s];
         }
+        pl_next += g.pz;
+        qz += g.pz;
+        out_pl += g.pz;
     };
     if (S::UNROLL) {  // four planes per trip: every slot a compile-time constant
         for (int zA = zlo; zA <= zhi + 1; zA += 4) {
