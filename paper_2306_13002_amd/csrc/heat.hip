@@ -109,22 +109,26 @@ __device__ __forceinline__ double heat3d7_sat_tile(const double *__restrict__ sr
     double nxt = ld ? src[col + (long long)(k0 + 2) * g.pz] : 0.0;
     halo.load(src + (long long)(k0 + 1) * g.pz);
     double acc = 0.0;
+    // running offset of plane zc (one 64-bit add per plane instead of a
+    // multiply per access)
+    long long zo = (long long)(k0 + R) * g.pz;
+    const long long pz = g.pz;
 
-    for (int k = k0; k < k1; ++k) {
+    for (int k = k0; k < k1; ++k, zo += pz) {
         const int zc = k + R;
         const int b = (k - k0) & 1;
         // stage plane zc: centre from the queue, ring from the stager
         tile[b][me] = cur;
         halo.store(tile[b]);
         // bulk load: every global load of the next plane before this plane's math
-        const double nn = (ld && zc + 2 < PZ) ? src[col + (long long)(zc + 2) * g.pz] : 0.0;
-        if (k + 1 < k1) halo.load(src + (long long)(zc + 1) * g.pz);
+        const double nn = (ld && zc + 2 < PZ) ? src[col + zo + 2 * pz] : 0.0;
+        if (k + 1 < k1) halo.load(src + zo + pz);
         __syncthreads();
         if (in) {
             const double *t = tile[b];
             const double s = ((t[me - 1] + t[me + 1]) + (t[me - W] + t[me + W])) + (prv + nxt);
             const double v = fma(cn, s, cc * cur);
-            dst[col + (long long)zc * g.pz] = v;
+            dst[col + zo] = v;
             const double d = v - cur;
             acc = fma(d, d, acc);
         }
