@@ -323,6 +323,132 @@ def test_poisson19_f32store_rounds_state():
     assert abs(g32 - g64) <= 1e-4 * g64
 
 
+def _round_f32(x: Fraction) -> Fraction:
+    """x rounded to the nearest float32 (ties to even), as an exact rational:
+    the float32 candidates around a first guess are compared exactly, so no
+    double rounding through float64 can creep in."""
+    f = np.float32(float(x))
+    cands = [f, np.nextafter(f, np.float32(np.inf)), np.nextafter(f, np.float32(-np.inf))]
+    best = None
+    for c in cands:
+        d = abs(Fraction(float(c)) - x)
+        even = (int(np.array(c, np.float32).view(np.uint32)) & 1) == 0
+        if best is None or d < best[0] or (d == best[0] and even):
+            best = (d, c)
+    return Fraction(float(best[1]))
+
+
+def test_poisson19_f32store_one_dimensional_reduction_exact():
+    # F32 storage rounds the state after EVERY sweep: inside the light cone
+    # the F32STORE run follows q_t = fl32(q + w*(a3*(4q(k) + q(k+1) + q(k-1)) - q)),
+    # fl32 a correct rounding to float32 of the exact rational.  With a3 = 1/8
+    # and w = 3/4 every FP64 operation of a sweep on float32 data is exact
+    # (at most ~30 significant bits), so FP64 arithmetic followed by the store
+    # rounding IS that correct rounding.  (With w = 0.8 the exact value can sit
+    # on a float32 tie that FP64 rounding of w*ss breaks differently.)  A state
+    # rounded only once at the end, or only on input, drifts off this
+    # recurrence by float32 ulps from the second sweep on.
+    K, nxy, T = 65, 13, 6
+    p, coefs = synth.poisson19_inputs((K, nxy, nxy), values=dict(a3=0.125))
+    a3 = Fraction(1, 8)
+    w = Fraction(3, 4)
+    q = [Fraction(k * k, (K - 1) ** 2) for k in range(K)]
+    assert all(_round_f32(v) == v for v in q)  # the initial state is exact in float32
+    n = nxy - 2
+    rounded = 0
+    for t in range(1, T + 1):
+        nq = [q[0]]
+        for k in range(1, K - 1):
+            v = q[k] + w * (a3 * (4 * q[k] + q[k + 1] + q[k - 1]) - q[k])
+            nq.append(_round_f32(v))
+            rounded += nq[-1] != v
+        q = nq + [q[-1]]
+        out, _ = oracle.poisson19(p, coefs, 0.75, t, mode="F32STORE")
+        want = np.array([float(v) for v in q[1:K - 1]])
+        inner = interior(out, 1)
+        for j in range(n):
+            for i in range(n):
+                if min(i, j, n - 1 - i, n - 1 - j) >= t - 1:
+                    assert np.array_equal(inner[:, j, i], want), (t, j, i)
+    assert rounded > (K - 2) * T // 4  # the store rounding really acts (136 of 378 updates)
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 4])
+def test_poisson19_f32store_is_one_rounding_per_sweep(T):
+    # T sweeps in F32STORE mode = T times (one FP64 sweep, then round the
+    # state to float32), and the residual is that of the last such sweep.
+    # Random coefficients, b terms nonzero.
+    p, coefs = synth.poisson19_random_inputs((12, 11, 10), seed=4)
+    assert any(np.any(coefs[i] != 0) for i in (4, 5, 6))
+    state = p.astype(np.float64)
+    g1 = None
+    for _ in range(T):
+        one, g1 = oracle.poisson19(state, coefs, 0.8, 1, mode="F64")
+        state = one.astype(np.float32).astype(np.float64)
+    o32, g32 = oracle.poisson19(p, coefs, 0.8, T, mode="F32STORE")
+    assert np.array_equal(o32, state)
+    assert g32 == g1
+
+
+def _dyadic_generic(r, box, seed):
+    """Taps, ids and coefficients for the float32-storage pins: coefficients
+    are multiples of 2^-8 summing to about 1, the field lies in [0.5, 1] and
+    is float32.  Every product then has at most 32 significant bits and every
+    partial sum stays far inside float64's 53, so any summation order gives
+    the exact value and only the float32 store rounds."""
+    rng = np.random.default_rng(seed)
+    taps = synth.box_taps(r) if box else synth.star_taps(r)
+    m = max(1, len(taps) // 3)
+    cid = rng.integers(0, m, size=len(taps)).astype(np.int32)
+    n_c = rng.integers(1, 9, size=m)
+    total = sum(int(n_c[c]) for c in cid)
+    coef = np.array([max(1, round(int(v) * 256 / total)) / 256.0 for v in n_c])
+    shape = (2 * r + 6, 2 * r + 5, 2 * r + 7)
+    u0 = (0.5 + 0.5 * synth.uniform_f32(seed, 0, shape)).astype(np.float32)
+    return np.array(taps, np.int32), cid, coef, u0
+
+
+@pytest.mark.parametrize("r,box", [(2, True), (4, False)])
+def test_generic_f32store_matches_correlate_rounded_per_sweep(r, box):
+    # Independent of the oracle: scipy's correlate (exact here, see
+    # _dyadic_generic) followed by a float32 rounding of the interior after
+    # every sweep; the halo keeps its float32 values.
+    taps, cid, coef, u0 = _dyadic_generic(r, box, 40 + r)
+    k = np.zeros((2 * r + 1,) * 3)
+    for (dx, dy, dz), c in zip(taps, cid):
+        k[dz + r, dy + r, dx + r] += coef[c]
+    ref = u0.astype(np.float64)
+    for T in (1, 2, 3):
+        nxt = ndi.correlate(ref, k, mode="constant")
+        interior(ref, r)[...] = interior(nxt, r).astype(np.float32).astype(np.float64)
+        out, res = oracle.generic(u0, r, taps, cid, coef, T, mode="F32STORE")
+        assert np.array_equal(out, ref), T
+
+
+@pytest.mark.parametrize("r,box", [(2, True), (4, False)])
+@pytest.mark.parametrize("T", [1, 2, 3, 4])
+def test_generic_f32store_is_one_rounding_per_sweep(r, box, T):
+    # T sweeps in F32STORE mode = T times (one FP64 sweep, then round to
+    # float32), with random (non-dyadic) coefficients; the residual is that of
+    # the stored (rounded) states of the last sweep.
+    rng = np.random.default_rng(60 + r)
+    taps = np.array(synth.box_taps(r) if box else synth.star_taps(r), np.int32)
+    m = max(1, len(taps) // 4)
+    cid = rng.integers(0, m, size=len(taps)).astype(np.int32)
+    coef = rng.random(m)
+    coef = coef / sum(coef[c] for c in cid)
+    u0 = synth.uniform_f32(7, r, (2 * r + 5, 2 * r + 6, 2 * r + 4))
+    state = u0.astype(np.float64)
+    prev = state
+    for _ in range(T):
+        one, _ = oracle.generic(state, r, taps, cid, coef, 1, mode="F64")
+        prev, state = state, one.astype(np.float32).astype(np.float64)
+    out, res = oracle.generic(u0, r, taps, cid, coef, T, mode="F32STORE")
+    assert np.array_equal(out, state)
+    d = interior(state, r) - interior(prev, r)
+    assert abs(res - np.sum(d * d)) <= 1e-13 * res
+
+
 # ---------------------------------------------------------------- wave25
 def test_wave25_impulse_response():
     c = synth.WAVE25_COEF
