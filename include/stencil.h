@@ -284,6 +284,24 @@ stencil_status stencil_mlp_predict(const float *model, const float *X, int32_t n
  * may try for d so later plans find them cached.  Other kinds: no-op. */
 stencil_status stencil_prepare(const stencil_desc *d);
 
+/* Streaming kernel of known traffic: the HBM ceiling of the sweeps' access
+ * shapes (and the known-size kernel that calibrates byte counters).  It is a
+ * measurement aid beside the sweeps, defined by the bytes it moves:
+ *   op 0: d[i] = a[i]                          (8 B read, 8 B written per element)
+ *   op 1: d[i] = fma(c[i], a[i], 2*a[i] - b[i])  (24 B read, 8 B written) --
+ *         the leapfrog step's shape: three FP64 grids read, one written, and
+ *         d may be b (written in place, as WAVE25 overwrites u^{n-1}).
+ * a, b, c, d: DEVICE pointers to n doubles each (b, c unused by op 0), owned
+ * by the caller, aligned to 8*width bytes; d must not overlap a or c, nor b
+ * unless d == b.  width: doubles per lane and access (1: 8-byte loads and
+ * stores, 2: 16-byte).  flags: bit 0 nontemporal loads, bit 1 nontemporal
+ * stores.  grid: blocks of 256 threads in a grid-stride loop; 0 = enough
+ * blocks for one element group per thread.  Asynchronous on `stream`;
+ * E_INVAL for bad arguments (nothing enqueued), E_DEVICE for no GPU or a
+ * failed launch. */
+stencil_status stencil_stream(int32_t op, const double *a, const double *b, const double *c, double *d, int64_t n,
+                              int32_t width, int32_t flags, int32_t grid, void *stream);
+
 /* Release a plan and its buffers (waits for nothing; the caller must not
  * destroy a plan while its work is in flight).  NULL is accepted. */
 stencil_status stencil_destroy(stencil_plan_t p);

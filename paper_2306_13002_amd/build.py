@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libstencil.so")
-SOURCES = ["abi.cpp", "tune.cpp", "batch.cpp", "support.hip", "heat.hip", "poisson19.hip", "wave25.hip", "generic.hip", "costmodel.hip", "costmodel_host.cpp", "rtc.cpp", "saturator.cpp", "program.cpp"]
+SOURCES = ["abi.cpp", "tune.cpp", "batch.cpp", "support.hip", "heat.hip", "poisson19.hip", "wave25.hip", "generic.hip", "stream.hip", "costmodel.hip", "costmodel_host.cpp", "rtc.cpp", "saturator.cpp", "program.cpp"]
 ARCH = os.environ.get("STENCIL_OFFLOAD_ARCH", "gfx950")
 
 CXXFLAGS = [

@@ -102,12 +102,13 @@ int default_remap(int) { return 1; }
 // id), groups ordered by dz slot then id, taps in a group by address.
 stencil_status build_generic_tables(stencil_plan_s *p, const stencil_desc *d) {
     const int n = d->n_taps, r = p->g.r, ns = 2 * r + 1;
-    std::vector<int> off(n), slot_g(ns + 1, 0), g_t, t_xy;
+    std::vector<int> slot_g(ns + 1, 0), g_t, t_xy;
+    std::vector<long long> off(n);  // 64-bit: a plane pitch may exceed INT_MAX / r
     std::vector<double> c(n), g_c;
     unsigned h = 2166136261u;
     for (int t = 0; t < n; ++t) {
         const int dx = d->tap_off[3 * t], dy = d->tap_off[3 * t + 1], dz = d->tap_off[3 * t + 2];
-        off[t] = (int)(dz * p->g.pz + dy * p->g.py + dx);
+        off[t] = (long long)dz * p->g.pz + (long long)dy * p->g.py + dx;
         c[t] = d->coef[d->tap_cid[t]];
         for (int v : {dx, dy, dz, d->tap_cid[t]}) h = (h ^ (unsigned)v) * 16777619u;
     }
@@ -128,16 +129,18 @@ stencil_status build_generic_tables(stencil_plan_s *p, const stencil_desc *d) {
     }
     slot_g[ns] = (int)g_c.size();
     g_t.push_back((int)t_xy.size());
-    // one buffer: [off n][slot_g ns+1][g_t ng+1][t_xy n] (ints), then doubles [c n][g_c ng]
-    const size_t ni = off.size() + slot_g.size() + g_t.size() + t_xy.size();
+    // one buffer: [slot_g ns+1][g_t ng+1][t_xy n] (ints), then 8-byte words
+    // [off n] (int64), [c n][g_c ng] (doubles)
+    const size_t ni = slot_g.size() + g_t.size() + t_xy.size();
     const size_t ib = ((ni * sizeof(int)) + 15) & ~size_t(15);
-    const size_t total = ib + (c.size() + g_c.size()) * sizeof(double);
+    const size_t total = ib + (off.size() + c.size() + g_c.size()) * 8;
     std::vector<char> host(total, 0);
     int *ip = (int *)host.data();
     size_t o = 0;
     auto put = [&](const std::vector<int> &v) { std::memcpy(ip + o, v.data(), v.size() * sizeof(int)); size_t at = o; o += v.size(); return at; };
-    const size_t o_off = put(off), o_slot = put(slot_g), o_gt = put(g_t), o_xy = put(t_xy);
-    double *dp = (double *)(host.data() + ib);
+    const size_t o_slot = put(slot_g), o_gt = put(g_t), o_xy = put(t_xy);
+    std::memcpy(host.data() + ib, off.data(), off.size() * sizeof(long long));
+    double *dp = (double *)(host.data() + ib + off.size() * sizeof(long long));
     std::memcpy(dp, c.data(), c.size() * sizeof(double));
     std::memcpy(dp + c.size(), g_c.data(), g_c.size() * sizeof(double));
     hipError_t e;
@@ -146,9 +149,10 @@ stencil_status build_generic_tables(stencil_plan_s *p, const stencil_desc *d) {
     if ((e = hipMemcpy(p->d_tab, host.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "hipMemcpy tap tables");
     const int *di = (const int *)p->d_tab;
-    const double *dd = (const double *)((const char *)p->d_tab + ib);
+    const long long *dl = (const long long *)((const char *)p->d_tab + ib);
+    const double *dd = (const double *)(dl + off.size());
     GenTab &t = p->base_args.gen;
-    t.off = di + o_off;
+    t.off = dl;
     t.c = dd;
     t.n = n;
     t.slot_g = di + o_slot;
@@ -262,6 +266,23 @@ stencil_status validate_desc(const stencil_desc *d, Geom &g, int &rz) {
     g.pz = pz;
     rz = nd == 3 ? r : 0;
     return STENCIL_OK;
+}
+
+// The host-side fields of a plan for a validated descriptor (no device call).
+void init_plan_fields(stencil_plan_s *p, const stencil_desc *d, const Geom &g, int rz) {
+    p->kind = d->kind;
+    p->dtype = d->dtype;
+    p->bc = d->bc;
+    p->g = g;
+    p->rz = rz;
+    p->omega = d->omega;
+    p->ops = ops_for(d->kind);
+    for (int c = 0; c < 5; ++c) p->c[c] = (d->coef && c < d->n_coef) ? d->coef[c] : 0.0;
+    p->info = stencil_info(d, g);
+    p->base_args.g = g;
+    for (int c = 0; c < 5; ++c) p->base_args.c[c] = p->c[c];
+    p->base_args.omega = d->omega;
+    p->base_args.elem_bytes = elem_bytes(d->dtype);
 }
 
 long long span_elems(const stencil_plan_s *p) {
@@ -380,6 +401,46 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     return STENCIL_OK;
 }
 
+// Check a single (non-batch) run's grid pointers against the plan and fill
+// the launch arguments.  Host only; nothing is enqueued.
+stencil_status prepare_run_args(const stencil_plan_s *p, void *const *fields, const void *const *coef_arrays,
+                                SweepArgs &a) {
+    if (!fields[0] || !fields[1]) return fail(STENCIL_E_INVAL, "fields[0] and fields[1] are required");
+    if (fields[0] == fields[1]) return fail(STENCIL_E_INVAL, "fields[0] and fields[1] must be distinct");
+    const int eb = elem_bytes(p->dtype);
+    for (int f = 0; f < 2; ++f)
+        if ((uintptr_t)fields[f] % eb) return fail(STENCIL_E_INVAL, "fields[%d] is not %d-byte aligned", f, eb);
+    // Both fields are written, so their padded spans must be disjoint, and a
+    // read-only coefficient grid must not overlap either of them.
+    const uintptr_t span = (uintptr_t)span_elems(p) * (uintptr_t)eb;
+    auto overlaps = [span](const void *x, const void *y, uintptr_t ybytes) {
+        const uintptr_t a0 = (uintptr_t)x, b0 = (uintptr_t)y;
+        return a0 < b0 + ybytes && b0 < a0 + span;
+    };
+    if (overlaps(fields[0], fields[1], span))
+        return fail(STENCIL_E_INVAL, "fields[0] and fields[1] overlap (padded span %lld elements)", span_elems(p));
+    a = p->base_args;
+    a.remap = p->remap;
+    if (p->kind == STENCIL_POISSON19) {
+        if (!coef_arrays) return fail(STENCIL_E_INVAL, "POISSON19 needs 12 coefficient arrays");
+        for (int c = 0; c < 12; ++c) {
+            if (!coef_arrays[c] || (uintptr_t)coef_arrays[c] % 4)
+                return fail(STENCIL_E_INVAL, "coefficient array %d is NULL or misaligned", c);
+            a.coefs[c] = coef_arrays[c];
+        }
+    } else if (p->kind == STENCIL_WAVE25) {
+        if (!coef_arrays || !coef_arrays[0] || (uintptr_t)coef_arrays[0] % 8)
+            return fail(STENCIL_E_INVAL, "WAVE25 needs coef_arrays = {vsq} (F64, aligned)");
+        a.coefs[0] = coef_arrays[0];
+    }
+    const int ncoef_arrays = p->kind == STENCIL_POISSON19 ? 12 : (p->kind == STENCIL_WAVE25 ? 1 : 0);
+    for (int c = 0; c < ncoef_arrays; ++c)
+        for (int f = 0; f < 2; ++f)
+            if (overlaps(fields[f], coef_arrays[c], span))
+                return fail(STENCIL_E_INVAL, "coefficient array %d overlaps fields[%d]", c, f);
+    return STENCIL_OK;
+}
+
 // The three parts of a run on stream s (enqueued eagerly or under capture).
 // Jacobi kinds first copy the state's halo into the scratch grid.
 hipError_t run_pre(stencil_plan_s *p, void *const *fields, hipStream_t s) {
@@ -478,19 +539,7 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out) {
     if (e != hipSuccess || ndev < 1) return fail(STENCIL_E_DEVICE, "no HIP device available");
     stencil_plan_s *p = new (std::nothrow) stencil_plan_s();
     if (!p) return fail(STENCIL_E_NOMEM, "host allocation failed");
-    p->kind = d->kind;
-    p->dtype = d->dtype;
-    p->bc = d->bc;
-    p->g = g;
-    p->rz = rz;
-    p->omega = d->omega;
-    p->ops = ops_for(d->kind);
-    for (int c = 0; c < 5; ++c) p->c[c] = (d->coef && c < d->n_coef) ? d->coef[c] : 0.0;
-    p->info = stencil_info(d, g);
-    p->base_args.g = g;
-    for (int c = 0; c < 5; ++c) p->base_args.c[c] = p->c[c];
-    p->base_args.omega = d->omega;
-    p->base_args.elem_bytes = elem_bytes(d->dtype);
+    init_plan_fields(p, d, g, rz);
     if ((e = hipGetDevice(&p->device)) != hipSuccess) {
         delete p;
         return hip_fail(e, "hipGetDevice");
@@ -524,26 +573,9 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
         if (!guard.ok) return fail(STENCIL_E_DEVICE, "cannot make device %d current", p->device);
         return batch_run(p, fields, iterations, (hipStream_t)stream_);
     }
-    if (!fields[0] || !fields[1]) return fail(STENCIL_E_INVAL, "fields[0] and fields[1] are required");
-    if (fields[0] == fields[1]) return fail(STENCIL_E_INVAL, "fields[0] and fields[1] must be distinct");
-    if (iterations < 0) return fail(STENCIL_E_INVAL, "iterations < 0");
-    const int eb = elem_bytes(p->dtype);
-    for (int f = 0; f < 2; ++f)
-        if ((uintptr_t)fields[f] % eb) return fail(STENCIL_E_INVAL, "fields[%d] is not %d-byte aligned", f, eb);
-    SweepArgs a = p->base_args;
-    a.remap = p->remap;
-    if (p->kind == STENCIL_POISSON19) {
-        if (!coef_arrays) return fail(STENCIL_E_INVAL, "POISSON19 needs 12 coefficient arrays");
-        for (int c = 0; c < 12; ++c) {
-            if (!coef_arrays[c] || (uintptr_t)coef_arrays[c] % 4)
-                return fail(STENCIL_E_INVAL, "coefficient array %d is NULL or misaligned", c);
-            a.coefs[c] = coef_arrays[c];
-        }
-    } else if (p->kind == STENCIL_WAVE25) {
-        if (!coef_arrays || !coef_arrays[0] || (uintptr_t)coef_arrays[0] % 8)
-            return fail(STENCIL_E_INVAL, "WAVE25 needs coef_arrays = {vsq} (F64, aligned)");
-        a.coefs[0] = coef_arrays[0];
-    }
+    SweepArgs a{};
+    stencil_status st = prepare_run_args(p, fields, coef_arrays, a);
+    if (st != STENCIL_OK) return st;
     if (iterations == 0) return STENCIL_OK;
     DeviceGuard guard(p->device);
     if (!guard.ok) return fail(STENCIL_E_DEVICE, "cannot make device %d current", p->device);
@@ -714,6 +746,31 @@ stencil_status stencil_prepare(const stencil_desc *d) {
     (void)hipFree(tmp.d_tab);
     delete tmp.rtc;
     return ok ? STENCIL_OK : STENCIL_E_DEVICE;
+}
+
+stencil_status stencil_stream(int32_t op, const double *a, const double *b, const double *c, double *d, int64_t n,
+                              int32_t width, int32_t flags, int32_t grid, void *stream) {
+    if (op != 0 && op != 1) return fail(STENCIL_E_INVAL, "stream op %d not in {0, 1}", op);
+    if (width != 1 && width != 2) return fail(STENCIL_E_INVAL, "stream width %d not in {1, 2}", width);
+    if (flags < 0 || flags > 3) return fail(STENCIL_E_INVAL, "stream flags %d not in 0..3", flags);
+    if (grid < 0) return fail(STENCIL_E_INVAL, "stream grid %d < 0", grid);
+    if (n < 0) return fail(STENCIL_E_INVAL, "stream n < 0");
+    if (!a || !d || (op == 1 && (!b || !c))) return fail(STENCIL_E_INVAL, "stream: a NULL array");
+    const uintptr_t al = 8u * (uintptr_t)width;
+    for (const void *q : {(const void *)a, (const void *)b, (const void *)c, (const void *)d})
+        if (q && (uintptr_t)q % al) return fail(STENCIL_E_INVAL, "stream arrays must be %d-byte aligned", (int)al);
+    // d is written: it must not overlap a read-only input (it may BE b, in place)
+    const uintptr_t bytes = (uintptr_t)n * 8u;
+    auto ov = [bytes](const void *x, const void *y) {
+        return x && y && (uintptr_t)x < (uintptr_t)y + bytes && (uintptr_t)y < (uintptr_t)x + bytes;
+    };
+    if (ov(d, a) || (op == 1 && ov(d, c)) || (op == 1 && d != b && ov(d, b)))
+        return fail(STENCIL_E_INVAL, "stream: d overlaps an input");
+    if (n == 0) return STENCIL_OK;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(STENCIL_E_DEVICE, "no HIP device available");
+    const hipError_t e = launch_stream(op, a, b, c, d, n, width, flags, grid, (hipStream_t)stream);
+    return e == hipSuccess ? STENCIL_OK : hip_fail(e, "stream launch");
 }
 
 stencil_status stencil_destroy(stencil_plan_t p) {

@@ -26,7 +26,7 @@ struct RtcSpec;  // generated saturated generic kernels (rtc.hpp)
 
 // GENERIC tap tables (device pointers, uniform over a launch).
 struct GenTab {
-    const int *off;     // plain: linear offset dz*pz + dy*py + dx per tap, caller's order
+    const long long *off;  // plain: linear offset dz*pz + dy*py + dx per tap, caller's order
     const double *c;    // plain: coefficient per tap
     int n;              // number of taps
     const int *slot_g;  // saturated: groups of z-offset slot s (dz = s - r) are [slot_g[s], slot_g[s+1])
@@ -92,6 +92,11 @@ constexpr int kReduceBlocks = 256;
 hipError_t launch_reduce_partials(const double *part, long long n, double *scratch, double *out, hipStream_t s);
 // out[p] = sum of part[seg[p] .. seg[count+p]) in a fixed order, p < count.
 hipError_t launch_segment_sums(const double *part, const int *seg, int count, double *out, hipStream_t s);
+
+// Streaming kernels of known traffic (stream.hip): op 0 copies a to d, op 1
+// writes d = fma(c, a, 2a - b) (three reads, one write; d may equal b).
+hipError_t launch_stream(int op, const double *a, const double *b, const double *c, double *d, long long n,
+                         int width, int flags, int grid, hipStream_t s);
 
 inline long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 

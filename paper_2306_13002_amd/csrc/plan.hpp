@@ -79,3 +79,19 @@ struct stencil_plan_s {
     RunGraphs *rg = nullptr;     // single plans: captured runs
     stn::StencilInfo info{};     // static description (cost-model features)
 };
+
+// Host-side steps of abi.cpp shared by the entry points (all host only unless
+// noted; the run_* functions enqueue on s).
+namespace stn {
+stencil_status fail(stencil_status st, const char *fmt, ...);
+stencil_status hip_fail(hipError_t e, const char *what);
+stencil_status validate_desc(const stencil_desc *d, Geom &g, int &rz);
+void init_plan_fields(stencil_plan_s *p, const stencil_desc *d, const Geom &g, int rz);
+stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d);
+stencil_status prepare_run_args(const stencil_plan_s *p, void *const *fields, const void *const *coef_arrays,
+                                SweepArgs &a);
+hipError_t run_pre(stencil_plan_s *p, void *const *fields, hipStream_t s);
+hipError_t run_sweeps(stencil_plan_s *p, void *const *fields, SweepArgs a, int iterations, hipStream_t s,
+                      int *launches);
+hipError_t run_post(stencil_plan_s *p, void *const *fields, int launches, hipStream_t s);
+}  // namespace stn

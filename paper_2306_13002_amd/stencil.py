@@ -86,6 +86,8 @@ def lib():
         L.stencil_mlp_predict.argtypes = [fp, fp, i32, fp, vp]
         L.stencil_prepare.argtypes = [ctypes.POINTER(StencilDesc)]
         L.stencil_prepare.restype = ctypes.c_int
+        L.stencil_stream.argtypes = [i32, vp, vp, vp, vp, ctypes.c_int64, i32, i32, i32, vp]
+        L.stencil_stream.restype = ctypes.c_int
         for f in (L.stencil_plan, L.stencil_run, L.stencil_residual, L.stencil_plan_config, L.stencil_plan_graph,
                   L.stencil_plan_use_graphs, L.stencil_batch_problem_config,
                   L.stencil_profile_enable, L.stencil_profile_read, L.stencil_destroy, L.stencil_plan_batch,
@@ -163,8 +165,9 @@ def _stream_handle(stream) -> int:
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
 
-class Plan:
-    """A built plan.  Grids are padded torch tensors (see include/stencil.h)."""
+class _GridLayout:
+    """The padded layout of one descriptor's grids and the checks of the
+    tensors handed to the library for it."""
 
     def __init__(self, kind: str, n: Sequence[int], **kw):
         self.kind = kind
@@ -172,13 +175,7 @@ class Plan:
         self.dtype = kw.get("dtype") or DEFAULT_DTYPE[kind]
         self.radius = int(kw.get("radius") if kw.get("radius") is not None else RADIUS.get(kind, 1))
         self.pitch = tuple(kw.get("pitch", (0, 0)))
-        desc, keep = make_desc(kind, n, **kw)
-        h = ctypes.c_void_p()
-        _check(lib().stencil_plan(ctypes.byref(desc), ctypes.byref(h)))
-        del keep
-        self._h = h
 
-    # layout --------------------------------------------------------------
     def padded_shape(self):
         r = self.radius
         if self.kind == "heat2d5":
@@ -212,10 +209,8 @@ class Plan:
             raise ValueError(f"{what} shape {tuple(t.shape)} != padded shape {self.padded_shape()}")
         return ctypes.c_void_p(t.data_ptr())
 
-    # calls ---------------------------------------------------------------
-    def run(self, fields, coef_arrays=None, iterations: int = 1, stream=None):
-        """Run `iterations` sweeps (asynchronous on `stream`, default: torch's
-        current stream).  For wave25, returns (older, newer) tensors."""
+    def _pointers(self, fields, coef_arrays):
+        """(field pointer array, coefficient pointer array or None)."""
         if len(fields) != 2:
             raise ValueError("two field tensors are required")
         fp = (ctypes.c_void_p * 2)(*[self._check_tensor(f, self.dtype, f"fields[{i}]") for i, f in enumerate(fields)])
@@ -228,6 +223,25 @@ class Plan:
             if coef_arrays is None or len(coef_arrays) != 1:
                 raise ValueError("wave25 needs coef_arrays = [vsq]")
             cp = (ctypes.c_void_p * 1)(self._check_tensor(coef_arrays[0], "f64", "vsq"))
+        return fp, cp
+
+
+class Plan(_GridLayout):
+    """A built plan.  Grids are padded torch tensors (see include/stencil.h)."""
+
+    def __init__(self, kind: str, n: Sequence[int], **kw):
+        super().__init__(kind, n, **kw)
+        desc, keep = make_desc(kind, n, **kw)
+        h = ctypes.c_void_p()
+        _check(lib().stencil_plan(ctypes.byref(desc), ctypes.byref(h)))
+        del keep
+        self._h = h
+
+    # calls ---------------------------------------------------------------
+    def run(self, fields, coef_arrays=None, iterations: int = 1, stream=None):
+        """Run `iterations` sweeps (asynchronous on `stream`, default: torch's
+        current stream).  For wave25, returns (older, newer) tensors."""
+        fp, cp = self._pointers(fields, coef_arrays)
         _check(lib().stencil_run(self._h, fp, cp, int(iterations), ctypes.c_void_p(_stream_handle(stream))))
         if self.kind == "wave25":
             return (fields[1], fields[0]) if iterations % 2 == 1 else (fields[0], fields[1])
@@ -439,3 +453,24 @@ def mlp_predict(model, X, stream=None):
     _check(lib().stencil_mlp_predict(_fptr(model), _fptr(X), X.shape[0], _fptr(out),
                                      ctypes.c_void_p(_stream_handle(stream))))
     return out
+
+
+# ---------------------------------------------------------------- streaming probe
+STREAM_OPS = {"copy": 0, "3r1w": 1}
+
+
+def stream(op: str, a, b, c, d, width: int = 1, nt_loads: bool = False, nt_stores: bool = False, grid: int = 0,
+           stream=None):
+    """Enqueue one streaming kernel of known traffic (see stencil_stream):
+    op "copy" writes d = a, "3r1w" writes d = fma(c, a, 2a - b); a, b, c, d
+    are float64 CUDA tensors of one size (b, c may be None for "copy"; d may
+    be b).  Asynchronous on the current stream."""
+    import torch
+    n = a.numel()
+    for t in (a, b, c, d):
+        if t is not None and (t.dtype != torch.float64 or not t.is_cuda or t.numel() != n or not t.is_contiguous()):
+            raise ValueError("stream: contiguous float64 CUDA tensors of one size are required")
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+    flags = (1 if nt_loads else 0) | (2 if nt_stores else 0)
+    _check(lib().stencil_stream(STREAM_OPS[op], ptr(a), ptr(b), ptr(c), ptr(d), n, int(width), flags, int(grid),
+                                ctypes.c_void_p(_stream_handle(stream))))

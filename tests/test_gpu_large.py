@@ -187,3 +187,34 @@ def test_tall_grids_beyond_65535_planes(dev, variant):
     w64, _ = oracle.poisson19(pp, cf, 0.8, T, mode="F64")
     assert maxrel(f[0].cpu().numpy().astype(np.float64)[1:-1, 1:-1, 1:-1], w64[1:-1, 1:-1, 1:-1]) <= 1e-5
 
+
+
+def test_generic_plain_plane_pitch_beyond_int32_offsets(dev):
+    from paper_2306_13002_amd.stencil import Plan
+
+    # A plane pitch of 6e8 elements: the z taps of a radius-4 star reach
+    # +-4 planes = +-2.4e9 elements, past the 32-bit range, so every tap
+    # offset must be 64-bit.  F32 storage, one interior plane, 19 GB per
+    # array (only the grid's rows are written; the gaps are never read).
+    r, n = 4, (40, 6, 1)
+    PX, PY, PZ = n[0] + 2 * r, n[1] + 2 * r, n[2] + 2 * r
+    py, pz = PX, 600_000_000
+    assert 4 * pz > 2 ** 31
+    taps = synth.star_taps(r)
+    cids = [0] + [1 + (i // 2) % 4 for i in range(len(taps) - 1)]
+    coef = [0.4, 0.05, 0.04, 0.03, 0.03]
+    dense = synth.uniform_f32(23, 0, (PZ, PY, PX))
+    want, wr = oracle.generic(dense, r, taps, cids, coef, 2, mode="F32STORE")
+    span = (PZ - 1) * pz + PY * py
+    f = [torch.empty(span, dtype=torch.float32, device=dev) for _ in range(2)]
+    for z in range(PZ):
+        f[0][z * pz: z * pz + PY * py] = torch.from_numpy(dense[z].ravel()).to(dev)
+    p = Plan("generic", n, variant="plain", dtype="f32", radius=r, coef=coef, taps=taps, cids=cids,
+             pitch=(py, pz))
+    p.run(f, iterations=2)
+    gr = p.residual()
+    p.close()
+    got = np.stack([f[0][z * pz: z * pz + PY * py].cpu().numpy().reshape(PY, PX) for z in range(PZ)])
+    del f
+    assert np.array_equal(got.astype(np.float64), want)
+    assert abs(gr - wr) <= 1e-10 * wr
