@@ -8,7 +8,7 @@
  * loaded into one e-graph (Sec. "E-Graph Creation"), saturated with the rule
  * set of Table tab:rule -- FMA1..FMA3, COMM-ADD, COMM-MUL, ASSOC-ADD1/2,
  * ASSOC-MUL1/2 -- plus constant folding (Sec. "Rewriting Rules"), under the
- * limits of Sec. Evaluation (10 000 e-nodes, 10 iterations, 10 s); the
+ * limits of Sec. Experimental Methodology (10 000 e-nodes, 10 iterations, 10 s); the
  * cheapest equal program is extracted under the cost model of Sec. "Cost
  * Model" (constant 0, input variable 1, arithmetic 10, memory access 100,
  * common e-classes counted once); temporaries are inserted and, in the bulk

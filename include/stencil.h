@@ -160,11 +160,14 @@ typedef struct {
 
 /* Build a plan: validate d (host only, no device call before validation
  * passes), choose variant and tile, allocate the plan's small buffers.
+ * Paper: the choice it stands for is the paper's -- run the loop body as
+ * written or in its rewritten form (Sec. Methodology Overview: the tool
+ * swaps the rewritten kernel into the directive code at compile time). 
  * On success *out is a new plan; on error *out = NULL. */
 stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out);
 
 /* Build one plan over `count` independent grids (HEAT3D7, Dirichlet), run
- * together: problems are grouped into size classes by their largest
+ * together (a serving extension; the paper defines no batched launch): problems are grouped into size classes by their largest
  * interior edge (<= 64, then buckets of 32); each class gets one form and
  * launch shape -- when ds[0].tune is not FIXED and ds[0] leaves the form or
  * shape open, by timing the class's own work-list kernel over all its
@@ -179,7 +182,10 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out);
  * bit-identical to its own single plan with the same form and shape. */
 stencil_status stencil_plan_batch(const stencil_desc *ds, int32_t count, stencil_plan_t *out);
 
-/* Run `iterations` sweeps asynchronously on `stream`.
+/* Run `iterations` sweeps asynchronously on `stream`.  Paper: one sweep is
+ * the data-parallel loop nest whose innermost body the paper rewrites (Sec.
+ * Program Representation, E-Graph Creation), in the plain form or after the
+ * rewrites of Sec. Optimization with Saturation and Code Generation.
  * fields (device pointers):
  *   HEAT*, GENERIC, POISSON19: fields[0] = state (in/out), fields[1] = a
  *     scratch grid of the same layout; the library first copies the halo of
@@ -201,7 +207,9 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
                            int32_t iterations, void *stream);
 
 /* Residual of the last sweep of the last run, FP64: sum over the interior of
- * (new - old)^2 (POISSON19: sum of ss^2).  Reduces the per-block partials in
+ * (new - old)^2 (POISSON19: sum of ss^2).  Paper: not defined there; it is
+ * the convergence sum that Jacobi-type loop nests of the paper's benchmark
+ * class accumulate, kept in FP64 as a reduction after the sweep.  Reduces the per-block partials in
  * a fixed order (bitwise reproducible), copies 8 bytes to the host and
  * synchronizes `stream`.  E_STATE if no sweep has run on this plan. */
 stencil_status stencil_residual(stencil_plan_t p, double *host_out, void *stream);
@@ -303,10 +311,12 @@ stencil_status stencil_stream(int32_t op, const double *a, const double *b, cons
                               int32_t width, int32_t flags, int32_t grid, void *stream);
 
 /* Release a plan and its buffers (waits for nothing; the caller must not
- * destroy a plan while its work is in flight).  NULL is accepted. */
+ * destroy a plan while its work is in flight).  NULL is accepted.
+ * (Library plumbing; no paper passage.) */
 stencil_status stencil_destroy(stencil_plan_t p);
 
-/* Description of the last error on this thread; never NULL. */
+/* Description of the last error on this thread; never NULL.  (Library
+ * plumbing; no paper passage.) */
 const char *stencil_last_error(void);
 
 /* Library version string, e.g. "0.1.0 gfx950". */

@@ -12,8 +12,8 @@
 //     a constant e-node).  Matches of one iteration are collected first and
 //     applied together, then congruence is restored ("rebuild"); the loop
 //     stops when an iteration changes nothing or at the limits of Sec.
-//     Evaluation (10 000 e-nodes, 10 iterations, 10 s).
-//   * Extraction (Sec. "Extraction"): the cost model of Sec. "Cost Model"
+//     Experimental Methodology (10 000 e-nodes, 10 iterations, 10 s).
+//   * Extraction (Sec. "Code Selection"): the cost model of Sec. "Cost Model"
 //     (constant 0, input variable 1, arithmetic 10, memory access 100) is
 //     minimized over the selection of one e-node per e-class, counting each
 //     e-class once however often it is used (the paper's ILP objective).

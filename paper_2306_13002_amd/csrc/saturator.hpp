@@ -48,7 +48,7 @@ struct Generated {
 
 enum Form { F_PLAIN = 0, F_CSE = 1, F_CSE_SAT = 2, F_CSE_BULK = 3, F_ACCSAT = 4, F_ACCSAT_Z = 5 };
 
-// Limits of the saturation (the paper's Sec. Evaluation settings).
+// Limits of the saturation (the paper's Sec. Experimental Methodology settings).
 struct Limits {
     int max_nodes = 10000;
     int max_iters = 10;
