@@ -1,18 +1,23 @@
 """Benchmark: grid-point updates/s of the stencil sweeps on one MI355X.
 
-Default workload: the 19-point variable-coefficient pressure relaxation on a
-129 x 129 x 257 grid (boundary included; interior 127 x 127 x 255), F32
-storage with FP64 arithmetic and FP64 residual, omega 0.8, 20 sweeps per
-step, saturated form (the plain form is timed beside it).  One step = one
-stencil_run of 20 sweeps plus the residual read-back.  Inputs are resident
-in HBM before timing starts.
+Default workload (the headline): the radius-4 25-point leapfrog wave update,
+FP64, 512^3 interior + 4-cell halo, 10 steps per benchmark step, saturated
+form at its autotuned launch shape, the plain form timed beside it.  One
+step = one stencil_run of 10 steps plus the FP64 residual read-back; inputs
+are resident in HBM before timing starts.  Before timing, each form runs the
+workload once from the seeded inputs; the CPU-baseline leg runs the oracle on
+light-cone crops of that run and reports the max relative error (saturated
+<= 1e-12, plain bit-identical) beside the oracle's own throughput.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-Prints one JSON line.  Other workloads (--workload wave25 | heat2d5 |
-heat3d7 | batch | copy) exist for profiling runs of their kernels; --workload
-lhs times the saturator's block-tridiagonal assembly program (162^3, 75
-statements) in the five forms of the paper's ablation.
+Prints one JSON line.  The headline line also carries secondary objects:
+streaming ceilings of the sweeps' access shapes, poisson19 129x129x257 (F32
+storage, Infinity-Cache resident), heat3d7 160^3 and the 64-grid heat3d7
+batch.  --workload poisson19 | heat3d7 | heat2d5 | batch | generic | stream |
+copy times one of them alone (for profiling runs); --workload lhs times the
+saturator's block-tridiagonal assembly program (162^3, 75 statements) in the
+five forms of the paper's ablation.
 """
 from __future__ import annotations
 
@@ -27,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+INFINITY_CACHE_BYTES = 256 << 20  # MI355X Infinity Cache (MALL)
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X published FP64 vector peak
 # Launch shapes come from the library's exhaustive autotuner at plan time
 # (outside the timed region), separately for each form.
@@ -104,8 +110,8 @@ def setup_workload(name, variant, dev, torch, synth, Plan, plan_kw=None):
 
         meta = dict(workload="wave25 radius-4 leapfrog, 512^3 interior + 4-cell halo, FP64, 10 steps + residual",
                     interior=list(n), iterations=T, bytes_per_update=32,
-                    kernel_tag=f"wave25_{'sat' if variant == 'saturated' else 'plain'}_512c", source="wave25.hip",
-                    storage="f64")
+                    kernel_tag=f"wave25_{'sat' if variant == 'saturated' else 'plain'}_512c",
+                    source=("wave25.hip", "common.hpp"), storage="f64")
         return plan, step, (lambda: None), n[0] * n[1] * n[2] * T, T, meta
     if name in ("heat2d5", "heat3d7"):
         if name == "heat2d5":
@@ -532,20 +538,414 @@ def bench_lhs(a, torch):
     print(json.dumps(out), flush=True)
 
 
+
+METRIC = "grid-point updates/s + % HBM peak, saturated vs plain, at max rel err 1e-12 FP64"
+
+# ---------------------------------------------------------------- wave25 headline
+W25_N = (512, 512, 512)
+W25_T = 10
+# interior boxes [lo, hi) (x, y, z) compared with the oracle: a corner, the
+# centre, and two boxes touching other faces and edges
+W25_BOXES = [((0, 0, 0), (12, 9, 7)), ((250, 251, 249), (262, 259, 257)), ((500, 3, 505), (512, 11, 512)),
+             ((100, 506, 0), (108, 512, 6))]
+
+
+def maxrel(got, want) -> float:
+    """max |got - want| / |want|; a nonzero value where want == 0 is infinite."""
+    import numpy as np
+
+    g = np.asarray(got, dtype=np.float64)
+    w = np.asarray(want, dtype=np.float64)
+    den = np.abs(w)
+    if np.any((den == 0) & (g != 0)):
+        return float("inf")
+    den = np.where(den == 0, 1.0, den)
+    return float(np.max(np.abs(g - w) / den)) if g.size else 0.0
+
+
+def crop_slices(n, lo, hi, r, margin):
+    """Padded-array slices (z, y, x) of a crop holding interior [lo, hi) plus
+    `margin` interior cells per side (clipped at the real halo) and an r-wide
+    halo, and the offsets of [lo, hi) inside the crop's interior.  After T
+    leapfrog steps a point depends only on cells within 4T of it, and the
+    two starting levels within 4(T-1), so a margin of 4(T-1) reproduces the
+    full-grid values of [lo, hi) exactly."""
+    sl, off = [], []
+    for ax in range(3):
+        a0 = max(lo[ax] - margin, 0)
+        a1 = min(hi[ax] + margin, n[ax])
+        sl.append(slice(a0, a1 + 2 * r))
+        off.append((lo[ax] - a0, hi[ax] - a0))
+    return tuple(reversed(sl)), tuple(reversed(off))
+
+
+def region(lo, hi, r):
+    """Padded-array slices (z, y, x) of interior [lo, hi)."""
+    return tuple(slice(l + r, h + r) for l, h in reversed(list(zip(lo, hi))))
+
+
+def timed(plan, step, reset, steps, warmup, torch):
+    """W untimed steps, then K steps timed by the wall clock (synchronized on
+    both sides) and by the plan's HIP events around its sweep launches on
+    the stream they are launched on."""
+    plan.profile(True)
+    for _ in range(warmup):
+        reset()
+        step()
+    reset()
+    torch.cuda.synchronize()
+    sweep_ms, sweeps, per = 0.0, 0, []
+    resid = None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        resid = step()
+        ms, n = plan.profile_read()
+        sweep_ms += ms
+        sweeps += n
+        per.append(ms / max(1, n))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per.sort()
+    return dict(wall=wall, sweep_ms=sweep_ms, sweeps=sweeps, resid=resid, sweep_ms_median=per[len(per) // 2],
+                sweep_ms_best=per[0])
+
+
+def host_info():
+    """CPU model (lscpu, else /proc/cpuinfo) and core counts of this host."""
+    import subprocess
+
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if not model:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cores_available": aff}
+
+
+def wave25_oracle_leg(a, b, v, gpu_regions, T):
+    """The CPU-baseline leg of the headline: the oracle on the light-cone
+    crops of the checked run (its outputs are compared with the GPU's) and on
+    a 128^3 crop of the same recipe for about 10 s more, single thread, then
+    the same crop calls on every core.  Returns (cpu_baseline, max rel err
+    per form)."""
+    import numpy as np
+
+    import oracle
+    from paper_2306_13002_amd import synth
+
+    errs = {form: 0.0 for form in gpu_regions}
+    pts = 0
+    t0 = time.perf_counter()
+    for bi, (lo, hi) in enumerate(W25_BOXES):
+        sl, off = crop_slices(W25_N, lo, hi, 4, 4 * (T - 1))
+        A, B, _ = oracle.wave25(a[sl], b[sl], v[sl], synth.WAVE25_COEF, T)
+        pts += int(np.prod([s - 8 for s in A.shape])) * T
+        cmp = tuple(slice(o0 + 4, o1 + 4) for o0, o1 in off)
+        for form, regs in gpu_regions.items():
+            ga, gb = regs[bi]
+            errs[form] = max(errs[form], maxrel(ga, A[cmp]), maxrel(gb, B[cmp]))
+    dt_crops = time.perf_counter() - t0
+    c = 128
+    ca, cb, cv = (x[:c + 8, :c + 8, :c + 8].copy() for x in (a, b, v))
+    t = time.perf_counter()
+    oracle.wave25(ca, cb, cv, synth.WAVE25_COEF, 1)
+    one = time.perf_counter() - t
+    k = max(1, min(200, int(10.0 / max(one, 1e-3))))
+    t = time.perf_counter()
+    oracle.wave25(ca, cb, cv, synth.WAVE25_COEF, k)
+    dt = time.perf_counter() - t
+    ac = all_cores(lambda: oracle.wave25(ca, cb, cv, synth.WAVE25_COEF, 2), c ** 3 * 2, 2 * one,
+                   f"2 steps of the {c}^3 crop")
+    total_pts = pts + c ** 3 * k
+    cpu = dict(value=total_pts / (dt_crops + dt), unit="grid-point updates/s", cores=1, kind="oracle",
+               sample=f"the oracle, single thread: {len(W25_BOXES)} light-cone crops of the checked 512^3 run "
+                      f"({pts} updates, {dt_crops:.1f} s; compared with the GPU) and a {c}^3 crop of the same "
+                      f"recipe for {k} steps ({c ** 3 * k} updates, {dt:.1f} s)",
+               host=host_info(), all_cores=ac)
+    return cpu, errs
+
+
+def wave25_headline(a, torch, synth, Plan, dev):
+    """The metric's configuration: saturated and plain wave25 at 512^3."""
+    import numpy as np
+
+    T = W25_T
+    pts_step = W25_N[0] * W25_N[1] * W25_N[2] * T
+    ha, hb, hv = synth.wave25_inputs(W25_N[0])
+    f = [torch.empty(ha.shape, dtype=torch.float64, device=dev) for _ in range(2)]
+    vs = torch.tensor(hv, device=dev)
+    src = [torch.tensor(ha, device=dev), torch.tensor(hb, device=dev)]  # the seeded start, kept on the device
+    forms = ["saturated"] if a.no_plain else ["saturated", "plain"]
+    res, regions, resid_check = {}, {}, {}
+    for form in forms:
+        print(f"[bench] wave25 {form}: plan (tuning)", file=sys.stderr, flush=True)
+        plan = Plan("wave25", W25_N, variant=form, coef=synth.WAVE25_COEF, tune=TUNE)
+        print(f"[bench] wave25 {form}: {plan.config()}; checked run, then timing", file=sys.stderr, flush=True)
+        # the checked run: T steps from the seeded start at the timed launch shape
+        for i in range(2):
+            f[i].copy_(src[i])
+        plan.run(f, [vs], iterations=T)
+        gr = plan.residual()
+        regions[form] = [(f[0][region(lo, hi, 4)].cpu().numpy(), f[1][region(lo, hi, 4)].cpu().numpy())
+                         for lo, hi in W25_BOXES]
+        # the residual against the returned fields (on the device, FP64): the
+        # two-pass reduction at the benchmarked size
+        newest, older = (f[0], f[1]) if T % 2 == 1 else (f[1], f[0])
+        d = newest[4:-4, 4:-4, 4:-4] - older[4:-4, 4:-4, 4:-4]
+        rs = float((d * d).sum())
+        del d
+        resid_check[form] = {"library": gr, "from_fields": rs, "rel_err": abs(gr - rs) / rs}
+
+        def step(plan=plan):
+            plan.run(f, [vs], iterations=T)
+            return plan.residual()
+
+        r = timed(plan, step, lambda: None, a.steps, a.warmup, torch)
+        r["cfg"] = plan.config()
+        res[form] = r
+        if form == "plain" and not a.no_ablation:
+            # the paper's ablation forms (per point), at the plain form's tuned shape
+            abl = {}
+            for v in ("cse_sat", "cse_bulk", "accsat_point"):
+                with Plan("wave25", W25_N, variant=v, coef=synth.WAVE25_COEF, tile=tuple(r["cfg"]["tile"])) as pv:
+                    ra = timed(pv, lambda pv=pv: (pv.run(f, [vs], iterations=T), pv.residual())[1], lambda: None,
+                               max(2, a.steps // 4), 1, torch)
+                abl[v] = {"us_per_sweep": ra["sweep_ms"] * 1e3 / max(1, ra["sweeps"])}
+            res["ablation"] = abl
+        plan.close()
+    del src, f, vs
+    torch.cuda.empty_cache()
+    sat = res["saturated"]
+    launch_s = sat["sweep_ms"] / 1e3 / max(1, sat["sweeps"])
+    alg = 32.0 * W25_N[0] * W25_N[1] * W25_N[2]
+    achieved = alg / launch_s / 1e9
+    traffic = read_traffic("wave25_sat_512c", ("wave25.hip", "common.hpp"))
+    tx, ty, zb = sat["cfg"]["tile"]
+    value = pts_step * a.steps / sat["wall"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": sat["wall"] * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded recipe: v ~ U[1.5,4.5), vsq = (0.4 v/4.5)^2, u^-1 = u^0 = 1 + 0.1 U[0,1))",
+        "config": {
+            "workload": "wave25 radius-4 25-point leapfrog, FP64, 512x512x512 interior + 4-cell halo, 10 steps "
+                        "per benchmark step + FP64 residual",
+            "variant": "saturated", "tile": [tx, ty, zb], "tile_map": sat["cfg"].get("tile_map"),
+            "launch_shape": "autotuned (exhaustive, at plan time)", "interior": list(W25_N),
+            "iterations_per_step": T, "storage": "f64", "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": f"wave25_sat tile {tx}x{ty}, zblock {zb}", "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg, "bytes_per_update": 32, "updates_per_launch": alg / 32,
+            "avg_launch_us": launch_s * 1e6, "median_launch_us": sat["sweep_ms_median"] * 1e3,
+            "best_launch_us": sat["sweep_ms_best"] * 1e3,
+            "traffic_gbs": traffic / launch_s / 1e9 if traffic else None,
+            "traffic_over_algorithmic": traffic / alg if traffic else None,
+            "timing": "HIP events on the launch stream around the timed steps' sweep launches",
+        },
+        "residual": sat["resid"],
+        "residual_check": resid_check,
+    }
+    if "plain" in res:
+        pr = res["plain"]
+        pl = pr["sweep_ms"] / 1e3 / max(1, pr["sweeps"])
+        pv = pts_step * a.steps / pr["wall"]
+        out["plain"] = {"value": pv, "ms_per_step": pr["wall"] * 1e3 / a.steps, "avg_launch_us": pl * 1e6,
+                        "achieved_gbs": alg / pl / 1e9, "frac": alg / pl / 1e9 / HBM_PEAK_GBS,
+                        "tile": list(pr["cfg"]["tile"]),
+                        "traffic": read_traffic("wave25_plain_512c", ("wave25.hip", "common.hpp"))}
+        out["saturated_over_plain"] = value / pv
+        if "ablation" in res:
+            abl = {"plain": {"us_per_sweep": pl * 1e6}, **res["ablation"],
+                   "saturated": {"us_per_sweep": launch_s * 1e6}}
+            for v in abl.values():
+                v["algorithmic_gbs"] = alg / (v["us_per_sweep"] * 1e-6) / 1e9
+            out["ablation"] = abl
+    tol = {"saturated": 1e-12, "plain": 0.0}
+    if not a.no_cpu:
+        print("[bench] oracle leg (light-cone crops, CPU baseline)", file=sys.stderr, flush=True)
+        cpu, errs = wave25_oracle_leg(ha, hb, hv, regions, T)
+        out["cpu_baseline"] = cpu
+        ok = all(errs[k] <= tol[k] for k in errs) and all(c["rel_err"] <= 1e-10 for c in resid_check.values())
+        out["parity"] = {"oracle": f"CPU FP64 oracle on {len(W25_BOXES)} light-cone crops of the same 512^3 run "
+                                   "(corner, centre, faces and edges), both time levels",
+                         "max_rel_err": errs, "tolerance": tol, "residual_tolerance": 1e-10, "pass": ok}
+    else:
+        out["parity"] = {"pass": None, "note": "not checked (--no-cpu skips the oracle leg)"}
+    return out
+
+
+# ---------------------------------------------------------------- streaming ceilings
+STREAM_VARIANTS = [  # (op, width, nt_loads, nt_stores, in_place)
+    ("3r1w", 1, False, False, True), ("3r1w", 2, False, False, True), ("3r1w", 1, True, True, True),
+    ("3r1w", 2, True, True, True), ("3r1w", 1, False, True, True), ("3r1w", 2, False, True, True),
+    ("3r1w", 1, False, False, False), ("copy", 1, False, False, False), ("copy", 2, False, False, False),
+    ("copy", 2, True, True, False),
+]
+
+
+def stream_ceilings(torch, dev, reps=10, edge=520):
+    """HBM ceilings of the sweeps' access shapes with the library's streaming
+    kernels on edge^3 FP64 arrays (the wave25 grid's storage): three reads +
+    one write in place (the leapfrog step), and copies (the Jacobi sweeps);
+    best and median of `reps` launches, HIP events on the launch stream."""
+    from paper_2306_13002_amd.stencil import stream
+
+    n = edge ** 3
+    A = torch.full((n,), 1.0, dtype=torch.float64, device=dev)
+    B = torch.full((n,), 0.5, dtype=torch.float64, device=dev)
+    C = torch.full((n,), 0.25, dtype=torch.float64, device=dev)
+    D = torch.empty(n, dtype=torch.float64, device=dev)
+    out = {}
+    for op, w, ntl, nts, inplace in STREAM_VARIANTS:
+        d = B if (op == "3r1w" and inplace) else D
+        bb, cc = (B, C) if op == "3r1w" else (None, None)
+        ms = []
+        for i in range(reps + 2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            stream(op, A, bb, cc, d, width=w, nt_loads=ntl, nt_stores=nts)
+            e1.record()
+            e1.synchronize()
+            if i >= 2:
+                ms.append(e0.elapsed_time(e1))
+        if op == "3r1w" and inplace:
+            B.fill_(0.5)
+        ms.sort()
+        nbytes = (32 if op == "3r1w" else 16) * n
+        name = f"{op}{'_inplace' if inplace else ''}_w{w}{'_ntload' if ntl else ''}{'_ntstore' if nts else ''}"
+        out[name] = {"bytes": nbytes, "best_us": ms[0] * 1e3, "median_us": ms[len(ms) // 2] * 1e3,
+                     "best_gbs": nbytes / (ms[0] * 1e-3) / 1e9, "median_gbs": nbytes / (ms[len(ms) // 2] * 1e-3) / 1e9}
+    del A, B, C, D
+    torch.cuda.empty_cache()
+    return {"arrays": f"{edge}^3 FP64 ({n * 8 / 2 ** 30:.3f} GiB each)", "kernel": "stencil_stream (stream.hip)",
+            "variants": out}
+
+
+# ---------------------------------------------------------------- secondary workloads
+def secondary_jacobi(name, a, dev, torch, synth, Plan):
+    """poisson19 129x129x257 or heat3d7 160^3: every form, tuned; per-pass and
+    per-sweep-equivalent fractions kept apart; cache residency flagged."""
+    forms = ["plain", "saturated", "saturated_t2"]
+    steps = max(5, a.steps // 2)
+    rows = {}
+    meta = None
+    for v in forms:
+        r = time_variant(name, v, steps, 2, dev, torch, synth, Plan)
+        meta = r["meta"]
+        per_launch = meta.get("sweeps_per_launch", 1)
+        sweep_s = r["sweep_ms"] / 1e3 / max(1, r["sweeps"])
+        launch_s = sweep_s * per_launch
+        pts_sweep = r["pts"] / r["T"]
+        alg = meta["bytes_per_update"] * pts_sweep
+        traffic = read_traffic(meta["kernel_tag"], meta["source"])
+        rows[v] = {"us_per_sweep": sweep_s * 1e6, "avg_launch_us": launch_s * 1e6, "sweeps_per_launch": per_launch,
+                   "tile": list(r["cfg"]["tile"]), "tile_map": r["cfg"].get("tile_map"),
+                   "updates_per_s": r["pts"] * steps / r["wall"],
+                   "frac_per_pass": alg / launch_s / 1e9 / HBM_PEAK_GBS,
+                   "frac_sweep_equivalent": alg * per_launch / launch_s / 1e9 / HBM_PEAK_GBS,
+                   "traffic_per_launch": traffic, "traffic_gbs": traffic / launch_s / 1e9 if traffic else None}
+    n_arrays = 14 if name == "poisson19" else 2
+    ws = n_arrays * (4 if meta["storage"] == "f32" else 8)
+    pts_total = 1
+    for e in (meta.get("grid_total") or [x + 2 for x in meta["interior"]]):
+        pts_total *= e
+    ws *= pts_total
+    return {
+        "workload": meta["workload"], "storage": meta["storage"], "working_set_bytes": ws,
+        "cache_resident": ws <= INFINITY_CACHE_BYTES,
+        "note": ("working set fits the 256 MB Infinity Cache: rates above are cache-assisted, not an HBM roofline"
+                 if ws <= INFINITY_CACHE_BYTES else "working set exceeds the Infinity Cache"),
+        "forms": rows,
+        # the paper's per-point rewrites vs. temporal blocking (two sweeps per pass, not in the paper)
+        "rewrite_gain_saturated_over_plain": rows["plain"]["us_per_sweep"] / rows["saturated"]["us_per_sweep"],
+        "temporal_blocking_gain_t2_over_saturated":
+            rows["saturated"]["us_per_sweep"] / rows["saturated_t2"]["us_per_sweep"],
+    }
+
+
+def secondary_batch(a, dev, torch, synth, Plan):
+    steps = max(3, a.steps // 4)
+    rows = {}
+    for v in ("saturated_t2", "plain"):
+        r = time_variant("batch", v, steps, 1, dev, torch, synth, Plan)
+        rows[v] = {"us_per_iteration": r["sweep_ms"] * 1e3 / max(1, r["sweeps"]),
+                   "updates_per_s": r["pts"] * steps / r["wall"], "ms_per_step": r["wall"] * 1e3 / steps}
+        if "classes" in r["cfg"]:
+            rows[v]["classes"] = [{"variant": c["variant"], "tile": list(c["tile"]), "problems": c["problems"]}
+                                  for c in r["cfg"]["classes"]]
+        pts = r["pts"] // r["T"]
+    alg = 16.0 * pts
+    for v in rows.values():
+        v["frac_per_sweep"] = alg / (v["us_per_iteration"] * 1e-6) / 1e9 / HBM_PEAK_GBS
+    return {"workload": "64 independent heat3d7 FP64 grids, edges 32..160 (seeded), 50 sweeps each + residuals",
+            "updates_per_iteration": pts, "working_set_bytes": 16 * pts,
+            "forms": {"batched_graph_two_sweep": rows["saturated_t2"], "separate_plain_runs": rows["plain"]},
+            "batched_over_separate": rows["plain"]["us_per_iteration"] / rows["saturated_t2"]["us_per_iteration"]}
+
+
+def run_secondary(out, a, dev, torch, synth, Plan):
+    sec = {}
+    for key, fn in (("stream", lambda: stream_ceilings(torch, dev)),
+                    ("poisson19", lambda: secondary_jacobi("poisson19", a, dev, torch, synth, Plan)),
+                    ("heat3d7", lambda: secondary_jacobi("heat3d7", a, dev, torch, synth, Plan)),
+                    ("batch", lambda: secondary_batch(a, dev, torch, synth, Plan))):
+        try:
+            sec[key] = fn()
+        except Exception as e:  # a secondary failure must not hide the headline
+            sec[key] = {"error": f"{type(e).__name__}: {e}"}
+        print(f"[bench] secondary {key} done", file=sys.stderr, flush=True)
+    out["secondary"] = sec
+    if "stream" in sec and "variants" in sec["stream"]:
+        v = sec["stream"]["variants"]
+        best = max(x["best_gbs"] for k, x in v.items() if k.startswith("3r1w_inplace"))
+        out["roofline"]["stream_ceiling_3r1w_gbs"] = best
+        out["roofline"]["frac_of_stream_ceiling"] = out["roofline"]["achieved"] / best
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="poisson19", choices=["poisson19", "wave25", "heat2d5", "heat3d7", "batch", "copy", "lhs", "generic"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="wave25",
+                    choices=["wave25", "poisson19", "heat2d5", "heat3d7", "batch", "copy", "lhs", "generic", "stream"])
     ap.add_argument("--variant", default="best", choices=["best", "saturated", "saturated_t2", "plain"],
-                    help="best: every saturated form the workload offers, tuned, the fastest reported")
+                    help="non-headline workloads: best = every saturated form the workload offers, tuned, the "
+                         "fastest reported")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain form beside it")
+    ap.add_argument("--no-ablation", action="store_true", help="wave25: skip the per-point ablation forms")
+    ap.add_argument("--no-secondary", action="store_true", help="wave25: only the headline, no secondary objects")
     ap.add_argument("--lhs-forms", default="plain,cse,cse_sat,cse_bulk,accsat,accsat_z",
                     help="lhs workload: the saturator forms to time")
     ap.add_argument("--lhs-zblock", default="8,16,32", help="lhs workload: z planes per thread tried for accsat_z")
     ap.add_argument("--lhs-tile", default="", help="lhs workload: one block shape 'tx,ty' instead of the search")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (and with it the oracle parity)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {a.gpus} requested); the stencil library has no "
@@ -561,6 +961,26 @@ def main():
     torch.cuda.set_device(dev)
     if a.workload == "lhs":
         return bench_lhs(a, torch)
+    if a.workload == "stream":
+        print(json.dumps({"metric": "HBM streaming ceiling (GB/s) of the sweeps' access shapes",
+                          "stream": stream_ceilings(torch, dev, reps=max(3, a.steps))}), flush=True)
+        return
+    if a.workload == "wave25" and a.variant in ("best", "saturated"):
+        out = wave25_headline(a, torch, synth, Plan, dev)
+        print("[bench] headline done", file=sys.stderr, flush=True)
+        if not a.no_secondary:
+            run_secondary(out, a, dev, torch, synth, Plan)
+        print(json.dumps(out), flush=True)
+        if out["parity"]["pass"] is False:
+            print("[bench] PARITY FAILURE against the oracle", file=sys.stderr, flush=True)
+            sys.exit(1)
+        return
+    bench_workload(a, dev, torch, synth, Plan)
+
+
+def bench_workload(a, dev, torch, synth, Plan):
+    """One workload alone (profiling runs): its saturated forms, the plain
+    form beside them, the oracle's CPU rate."""
     forms = [a.variant]
     if a.variant == "best":
         forms = ["saturated", "saturated_t2"] if a.workload in ("poisson19", "heat3d7", "batch") else ["saturated"]
@@ -600,7 +1020,7 @@ def main():
                 "fp64_instr_per_s": ins, "issue_frac": ins / (FP64_VECTOR_PEAK_TFLOPS * 1e12 / 2),
                 "hbm_gbs": alg_bytes / launch_s / 1e9}
     out = {
-        "metric": "grid-point updates/s (+ % of HBM peak), saturated vs plain",
+        "metric": METRIC if meta["storage"] == "f64" else "grid-point updates/s (+ % of HBM peak), saturated vs plain",
         "value": value,
         "unit": "grid-point updates/s",
         "n_gpus": 1,
@@ -610,7 +1030,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": meta["storage"],
+        "arithmetic": "f64",
         "data": "synthetic (seeded recipe of the workload)",
         "config": {
             "workload": meta["workload"],
@@ -654,7 +1075,7 @@ def main():
                         "achieved_gbs": meta["bytes_per_update"] * pts_per_sweep / pl / 1e9, "avg_launch_us": pl * 1e6,
                         "tile": list(pr["cfg"]["tile"]), "tile_map": pr["cfg"].get("tile_map")}
         out["saturated_over_plain"] = value / pv
-        if a.workload in ("poisson19", "wave25") and "saturated" in sat:
+        if a.workload == "poisson19" and "saturated" in sat:
             # the paper's ablation forms (per point), at the plain form's tuned shape
             abl = {"plain": {"us_per_sweep": pl * 1e6},
                    "saturated": {"us_per_sweep": sat["saturated"]["sweep_ms"] * 1e3 / max(1, sat["saturated"]["sweeps"])}}

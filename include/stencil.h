@@ -207,9 +207,9 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
                            int32_t iterations, void *stream);
 
 /* Residual of the last sweep of the last run, FP64: sum over the interior of
- * (new - old)^2 (POISSON19: sum of ss^2).  Paper: not defined there; it is
- * the convergence sum that Jacobi-type loop nests of the paper's benchmark
- * class accumulate, kept in FP64 as a reduction after the sweep.  Reduces the per-block partials in
+ * (new - old)^2 (POISSON19: sum of ss^2).  Paper: not defined there (it
+ * rewrites loop bodies and reports kernel times); this is the FP64 sum of
+ * squared updates a Jacobi-type solver checks for convergence.  Reduces the per-block partials in
  * a fixed order (bitwise reproducible), copies 8 bytes to the host and
  * synchronizes `stream`.  E_STATE if no sweep has run on this plan. */
 stencil_status stencil_residual(stencil_plan_t p, double *host_out, void *stream);
