@@ -78,6 +78,9 @@ typedef enum {
  * WAVE25    radius-4 star, second order in time (leapfrog), F64, r = 4:
  *             L(u) = sum over x,y,z of [c0*u + sum_{q=1..4} c_q*(u(+q) + u(-q))]
  *             u_next = 2u - u_prev + vsq*L(u);   coef = {c0,c1,c2,c3,c4}.
+ *           Its SATURATED kernel addresses a plane with 32-bit byte offsets:
+ *           pitch_z*8 above 0xFFFFFFF0 bytes is E_UNSUPPORTED for SATURATED
+ *           and makes AUTO choose PLAIN, which takes every plane size.
  * GENERIC   u'(x) = sum_t coef[cid_t] * u(x + delta_t), 3-D, radius 1..4,
  *           F32 or F64, taps given by tap_off/tap_cid.  Its saturated
  *           kernels are generated and launched through the module API,

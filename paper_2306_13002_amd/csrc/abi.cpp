@@ -350,15 +350,23 @@ struct DeviceGuard {
 
 stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     const KindOps *ops = p->ops;
-    const bool has_sat = ops->sat_tiles != nullptr;
+    bool has_sat = ops->sat_tiles != nullptr;
+    int dv = d->variant;
+    // the saturated leapfrog kernel addresses a plane with 32-bit byte offsets
+    if (p->kind == STENCIL_WAVE25 && p->g.pz * (long long)sizeof(double) > kMaxPlaneBytes32) {
+        if (dv == STENCIL_SATURATED)
+            return fail(STENCIL_E_UNSUPPORTED, "WAVE25 SATURATED needs pitch_z*8 <= %lld bytes (PLAIN takes any plane)",
+                        kMaxPlaneBytes32);
+        has_sat = false;
+        if (dv == STENCIL_AUTO) dv = STENCIL_PLAIN;
+    }
     if (d->tile_map < 0 || d->tile_map > 2) return fail(STENCIL_E_INVAL, "tile_map %d not in 0..2", d->tile_map);
-    if (d->variant == STENCIL_SATURATED && !has_sat)
+    if (dv == STENCIL_SATURATED && !has_sat)
         return fail(STENCIL_E_UNSUPPORTED, "kind %d has no saturated form", p->kind);
-    const bool open = !is_point_form(d->variant) &&
-                      (d->variant == STENCIL_AUTO || !d->tile_x || !d->tile_y || !d->zblock || !d->tile_map);
+    const bool open = !is_point_form(dv) && (dv == STENCIL_AUTO || !d->tile_x || !d->tile_y || !d->zblock || !d->tile_map);
     // the cost model has no timings of the two-sweep form: it is tuned exhaustively
-    if (d->tune == STENCIL_TUNE_MODEL && open && d->variant != STENCIL_SATURATED_T2) {
-        TuneRequest rq{has_sat ? d->variant : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map};
+    if (d->tune == STENCIL_TUNE_MODEL && open && dv != STENCIL_SATURATED_T2) {
+        TuneRequest rq{has_sat ? dv : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map};
         TuneEntry e{};
         stencil_status st = tune_model(p, rq, &e);
         if (st == STENCIL_OK) {
@@ -372,7 +380,7 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
         logf("%s; falling back to exhaustive tuning", stencil_last_error());
     }
     if ((d->tune == STENCIL_TUNE_EXHAUSTIVE || d->tune == STENCIL_TUNE_MODEL) && open) {
-        TuneRequest rq{has_sat ? d->variant : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map};
+        TuneRequest rq{has_sat ? dv : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map};
         const std::string key = tune_key(p, rq);
         TuneEntry e{};
         if (!tune_lookup(key, &e)) {
@@ -386,7 +394,7 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
         p->tuned = true;
         return STENCIL_OK;
     }
-    int v = d->variant;
+    int v = dv;
     if (v == STENCIL_AUTO) v = has_sat ? V_SATURATED : V_PLAIN;
     Tile t = default_tile(p->kind, is_point_form(v) ? V_PLAIN : v, p->g);
     if (d->tile_x) t.tx = d->tile_x;

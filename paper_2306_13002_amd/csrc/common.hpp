@@ -91,6 +91,24 @@ __device__ __forceinline__ void tile_coords(int remap, int &bx, int &by, int &bz
 }
 
 // ---------------------------------------------------------------------------
+// Raw buffer access to one plane: the plane's base address lives in a scalar
+// buffer resource (4 SGPRs) and each lane passes a 32-bit byte offset, so a
+// streaming kernel holds no 64-bit address per lane and per plane.  Word 3 is
+// the untyped 32-bit data format of gfx9-family raw buffers; the record count
+// is the full 32-bit range (offsets stay inside the plane, which the host
+// keeps below 4 GiB for kernels that use these).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *plane) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(plane), (short)0, -1, 0x00020000);
+}
+__device__ __forceinline__ double buf_ld_f64(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st_f64(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                          off, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
 // Halo stager: the cells of an xy tile's halo ring of width R (TX x TY
 // interior cells, LDS tile (TY+2R) x (TX+2R)), spread over the block's
 // threads.  With CORNERS = false the four R x R corner squares are skipped

@@ -100,4 +100,8 @@ hipError_t launch_stream(int op, const double *a, const double *b, const double 
 
 inline long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 
+// Largest plane (pitch_z * element size, bytes) that a kernel addressing a
+// plane with 32-bit byte offsets through a buffer resource accepts.
+constexpr long long kMaxPlaneBytes32 = 0xFFFFFFF0LL;
+
 }  // namespace stn

@@ -19,9 +19,10 @@
 // tile (BY thread rows, RY rows per thread) and streams z; each column keeps
 // the nine planes z-4..z+4 in a register queue (one global load per point),
 // the in-plane +-4 neighbours come from an LDS tile with a 4-cell ring (the
-// ring loaded four planes ahead, together with the queue heads, and held in
+// ring loaded five planes ahead, together with the queue heads, and held in
 // registers), and every load for the next plane (queue head, ring, u_prev,
-// vsq) is issued before the current plane is computed ("bulk load").
+// vsq) is issued before the current plane is computed ("bulk load"), into
+// staging registers first read one iteration later.
 #include "internal.hpp"
 
 namespace stn {
@@ -178,6 +179,20 @@ __global__ void wave25_point(const double *__restrict__ cur, double *__restrict_
     }
 }
 
+// Software pipeline: the loads of iteration k (queue head zc+5, u^{n-1} and
+// vsq of zc+1, ring of zc+5) go into one of two staging sets, chosen by the
+// parity of k - k0, and are first read -- used or moved -- at iteration k+1.
+// The z loop is unrolled by two so that the parity is a compile-time
+// constant; a single staging register moved into the queue at the end of its
+// own iteration would make every iteration wait for the loads it issued.
+// Every load is unconditional, so that no register is merged with an older
+// value: a lane outside the padded array reads a clamped cell of its row, and
+// a load for a plane past the block's range reads the current plane instead;
+// neither value is ever used (an interior point reads only cells of the padded
+// array).  Addresses: a wave-uniform pointer per plane stream, advanced one
+// plane per iteration, plus a per-thread 32-bit byte offset within the plane
+// (planes below 4 GiB, checked on the host), all loads and stores through
+// scalar buffer resources.
 template <int TX, int BY, int RY>
 __global__ __launch_bounds__(TX *BY) void wave25_sat(const double *__restrict__ cur, double *__restrict__ pn,
                                                      const double *__restrict__ vsq, Geom g, W25C c, int zb,
@@ -189,81 +204,85 @@ __global__ __launch_bounds__(TX *BY) void wave25_sat(const double *__restrict__ 
     tile_coords(remap, bx, by, bz);
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const int i = bx * TX + tx, jb = by * TY + ty * RY;
-    const int xp = i + R;
-    const int PX = g.nx + 2 * R, PY = g.ny + 2 * R, PZ = g.nz + 2 * R;
+    const int PX = g.nx + 2 * R, PY = g.ny + 2 * R;
     const int k0 = bz * zb, k1 = min(k0 + zb, g.nz);
 
-    bool in[RY], ld[RY];
-    long long col[RY];
+    bool in[RY];
+    unsigned colb[RY];  // byte offset of row m's column within a plane (clamped into the array)
     int me[RY];
 #pragma unroll
     for (int m = 0; m < RY; ++m) {
-        const int yp = jb + m + R;
+        const int yp = min(jb + m + R, PY - 1), xp = min(i + R, PX - 1);
         in[m] = i < g.nx && jb + m < g.ny;
-        ld[m] = xp < PX && yp < PY;
-        col[m] = (long long)yp * g.py + xp;
+        colb[m] = (unsigned)(((long long)yp * g.py + xp) * (long long)sizeof(double));
         me[m] = (ty * RY + m + R) * W + (tx + R);
     }
     HaloStager<double, TX, TY, R, false, NT> halo;
     halo.init(tid, bx * TX + R, by * TY + R, g.py, PX, PY);
+    constexpr int HR = decltype(halo)::HR;
+    unsigned hb[HR];  // byte offsets of this thread's ring cells (cells outside the array: offset 0)
+#pragma unroll
+    for (int h = 0; h < HR; ++h) hb[h] = halo.ok[h] ? (unsigned)(halo.goff[h] * (long long)sizeof(double)) : 0u;
+    const long long pzb = g.pz * (long long)sizeof(double);
+    auto at = [](const void *plane, unsigned off) -> double { return buf_ld_f64(plane_rsrc(plane), off); };
 
-    // q[m][s] = u^n at padded z = zc - 4 + s, zc = k + 4 the plane computed
-    double q[RY][9], up[RY], vv[RY];
+    // Iteration k computes padded plane zc = k + 4.  q[m][s]: u^n of row m's
+    // column at plane zc-4+s (s < 8); hd[P][m]: the queue head loaded at the
+    // last iteration of parity P; uq / vq: u^{n-1} and vsq likewise; hq[s]:
+    // this thread's ring cells of plane zc+s (s < 4), rg: the staged rings.
+    // At iteration k of parity P the staging sets 1-P hold plane zc+4 (head,
+    // ring) and plane zc (u^{n-1}, vsq), loaded at iteration k-1.
+    double q[RY][8], hd[2][RY], uq[2][RY], vq[2][RY], hq[4][HR], rg[2][HR];
+    const char *base = (const char *)cur + (long long)k0 * pzb;
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int m = 0; m < RY; ++m) q[m][s] = at(base + s * pzb, colb[m]);
 #pragma unroll
     for (int m = 0; m < RY; ++m) {
-#pragma unroll
-        for (int s = 0; s < 9; ++s) q[m][s] = ld[m] ? cur[col[m] + (long long)(k0 + s) * g.pz] : 0.0;
-        const long long o = col[m] + (long long)(k0 + R) * g.pz;
-        up[m] = in[m] ? pn[o] : 0.0;
-        vv[m] = in[m] ? vsq[o] : 0.0;
+        hd[1][m] = at(base + 2 * R * pzb, colb[m]);
+        uq[1][m] = at((const char *)pn + (long long)(k0 + R) * pzb, colb[m]);
+        vq[1][m] = at((const char *)vsq + (long long)(k0 + R) * pzb, colb[m]);
+        hd[0][m] = uq[0][m] = vq[0][m] = 0.0;
     }
-    // The ring cells of plane zc are loaded with the queue heads of plane
-    // zc (four planes before the plane is computed), when the neighbouring
-    // blocks load the same cells as their own queue heads, so the ring is
-    // mostly served from L2; hq[s] holds the ring of plane zc + s.
-    constexpr int HR = decltype(halo)::HR;
-    double hq[R + 1][HR];
+    // The ring cells of plane zc are loaded with the queue heads of plane zc,
+    // when the neighbouring blocks load the same cells as their own queue
+    // heads, so the ring is mostly served from L2.  Planes k0+4 .. k0+8 lie
+    // inside the array.
 #pragma unroll
-    for (int s = 0; s <= R; ++s) {
-        halo.load(cur + (long long)(k0 + R + s) * g.pz);
+    for (int h = 0; h < HR; ++h) {
 #pragma unroll
-        for (int h = 0; h < HR; ++h) hq[s][h] = halo.val[h];
+        for (int s = 0; s < 4; ++s) hq[s][h] = at(base + (R + s) * pzb, hb[h]);
+        rg[1][h] = at(base + 2 * R * pzb, hb[h]);
+        rg[0][h] = 0.0;
     }
     double acc = 0.0;
 
-    for (int k = k0; k < k1; ++k) {
-        const int zc = k + R, b = (k - k0) & 1;
-        double *t = tile[b];
+    // plane zc of u^n, of u^{n-1} (overwritten by u^{n+1}) and of vsq
+    const char *p_cur = (const char *)cur + (long long)(k0 + R) * pzb;
+    char *p_out = (char *)pn + (long long)(k0 + R) * pzb;
+    const char *p_vsq = (const char *)vsq + (long long)(k0 + R) * pzb;
+    auto step = [&](const int k, const int P) {
+        const int Q = 1 - P;
+        double *t = tile[P];
 #pragma unroll
         for (int m = 0; m < RY; ++m) t[me[m]] = q[m][4];
 #pragma unroll
-        for (int h = 0; h < HR; ++h) halo.val[h] = hq[0][h];
-        halo.store(t);
-        double upc[RY], vvc[RY], qn[RY];
-#pragma unroll
-        for (int m = 0; m < RY; ++m) {
-            upc[m] = up[m];
-            vvc[m] = vv[m];
-            qn[m] = 0.0;
-        }
-        if (k + 1 < k1) {  // bulk load of plane zc+1 (queue head zc+5)
-#pragma unroll
-            for (int m = 0; m < RY; ++m) qn[m] = (ld[m] && zc + 5 < PZ) ? cur[col[m] + (long long)(zc + 5) * g.pz] : 0.0;
-#pragma unroll
-            for (int s = 0; s < R; ++s)
-#pragma unroll
-                for (int h = 0; h < HR; ++h) hq[s][h] = hq[s + 1][h];
-            if (k + R + 1 < k1) {  // the ring of plane zc+5, computed at iteration k+5
-                halo.load(cur + (long long)(zc + R + 1) * g.pz);
-#pragma unroll
-                for (int h = 0; h < HR; ++h) hq[R][h] = halo.val[h];
-            }
+        for (int h = 0; h < HR; ++h)
+            if (halo.has[h]) t[halo.lidx[h]] = hq[0][h];
+        // bulk load into staging set P: head and ring of zc+5, u^{n-1} and vsq of zc+1
+        {
+            const long long o5 = k + 1 < k1 ? (R + 1) * pzb : 0;
+            const long long r5 = k + R + 1 < k1 ? (R + 1) * pzb : 0;
+            const long long o1 = k + 1 < k1 ? pzb : 0;
 #pragma unroll
             for (int m = 0; m < RY; ++m) {
-                const long long o = col[m] + (long long)(zc + 1) * g.pz;
-                up[m] = in[m] ? pn[o] : 0.0;
-                vv[m] = in[m] ? vsq[o] : 0.0;
+                hd[P][m] = at(p_cur + o5, colb[m]);
+                uq[P][m] = at(p_out + o1, colb[m]);
+                vq[P][m] = at(p_vsq + o1, colb[m]);
             }
+#pragma unroll
+            for (int h = 0; h < HR; ++h) rg[P][h] = at(p_cur + r5, hb[h]);
         }
         __syncthreads();
         // y neighbours that are rows of this same thread come from its own
@@ -276,28 +295,44 @@ __global__ __launch_bounds__(TX *BY) void wave25_sat(const double *__restrict__ 
         for (int m = 0; m < RY; ++m) {
             if (in[m]) {
                 const int e = me[m];
-                const double u = q[m][4];
+                const double uc = q[m][4];
                 const double s1 = ((t[e - 1] + t[e + 1]) + (yv(m, -1) + yv(m, 1))) + (q[m][3] + q[m][5]);
                 const double s2 = ((t[e - 2] + t[e + 2]) + (yv(m, -2) + yv(m, 2))) + (q[m][2] + q[m][6]);
                 const double s3 = ((t[e - 3] + t[e + 3]) + (yv(m, -3) + yv(m, 3))) + (q[m][1] + q[m][7]);
-                const double s4 = ((t[e - 4] + t[e + 4]) + (yv(m, -4) + yv(m, 4))) + (q[m][0] + q[m][8]);
-                double L = c.c0x3 * u;
+                const double s4 = ((t[e - 4] + t[e + 4]) + (yv(m, -4) + yv(m, 4))) + (q[m][0] + hd[Q][m]);
+                double L = c.c0x3 * uc;
                 L = fma(c.c1, s1, L);
                 L = fma(c.c2, s2, L);
                 L = fma(c.c3, s3, L);
                 L = fma(c.c4, s4, L);
-                const double nv = fma(vvc[m], L, 2.0 * u - upc[m]);
-                pn[col[m] + (long long)zc * g.pz] = nv;
-                const double d = nv - u;
+                const double nv = fma(vq[Q][m], L, 2.0 * uc - uq[Q][m]);
+                buf_st_f64(plane_rsrc(p_out), colb[m], nv);
+                const double d = nv - uc;
                 acc = fma(d, d, acc);
             }
         }
+        // advance: the queue takes the head of plane zc+4, the ring that of zc+4
 #pragma unroll
         for (int m = 0; m < RY; ++m) {
 #pragma unroll
-            for (int s = 0; s < 8; ++s) q[m][s] = q[m][s + 1];
-            q[m][8] = qn[m];
+            for (int s = 0; s < 7; ++s) q[m][s] = q[m][s + 1];
+            q[m][7] = hd[Q][m];
         }
+#pragma unroll
+        for (int h = 0; h < HR; ++h) {
+#pragma unroll
+            for (int s = 0; s < 3; ++s) hq[s][h] = hq[s + 1][h];
+            hq[3][h] = rg[Q][h];
+        }
+        p_cur += pzb;
+        p_out += pzb;
+        p_vsq += pzb;
+    };
+    for (int k = k0;; k += 2) {
+        if (k >= k1) break;
+        step(k, 0);
+        if (k + 1 >= k1) break;
+        step(k + 1, 1);
     }
     if (part) {
         const double s = block_sum_f64(acc, red);
