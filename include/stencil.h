@@ -209,6 +209,28 @@ stencil_status stencil_plan_batch(const stencil_desc *ds, int32_t count, stencil
 stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *const *coef_arrays,
                            int32_t iterations, void *stream);
 
+/* Allocation-free run, for callers that cannot allocate device or host
+ * memory during the call: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  The same sweeps, kernels and results as
+ * stencil_run (eagerly; graph replay is not used), but the per-block residual
+ * partials of the last sweep and the first pass of their reduction go to a
+ * fixed scratch array inside the library (one per GPU, 2^17 + 256 doubles,
+ * about 1 MiB, resident until the process ends), and the FP64 residual --
+ * the value stencil_residual would report -- is written to residual_dev, a
+ * DEVICE pointer owned by the caller (8 bytes, 8-byte aligned; NULL skips the
+ * reduction).  Only kernel launches are enqueued on `stream`; the call never
+ * synchronizes, allocates nothing and leaves the plan's own residual state
+ * (stencil_residual) as the last stencil_run left it.
+ * Limits: a plan whose sweep launch has more than 2^17 blocks (see
+ * stencil_plan_config; small tiles on large grids), batched plans and GENERIC
+ * plans running generated saturated kernels: E_UNSUPPORTED, checked before
+ * anything is enqueued.  Every call on one GPU shares that GPU's scratch and
+ * it keeps the last call's contents (each call writes every slot it reads):
+ * calls that overlap on one GPU -- concurrent streams, threads or graph
+ * replays -- race and must be serialized by the caller. */
+stencil_status stencil_run_noalloc(stencil_plan_t p, void *const *fields, const void *const *coef_arrays,
+                                   int32_t iterations, double *residual_dev, void *stream);
+
 /* Residual of the last sweep of the last run, FP64: sum over the interior of
  * (new - old)^2 (POISSON19: sum of ss^2).  Paper: not defined there (it
  * rewrites loop bodies and reports kernel times); this is the FP64 sum of

@@ -26,7 +26,7 @@ using namespace stn;
 
 namespace {
 
-thread_local std::string g_err = "no error";
+thread_local char g_err[512] = "no error";  // fixed size: reporting an error allocates nothing
 
 bool log_on() {
     static int v = -1;
@@ -47,7 +47,7 @@ stencil_status fail(stencil_status st, const char *fmt, ...) {
     va_start(ap, fmt);
     std::vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    g_err = buf;
+    std::memcpy(g_err, buf, sizeof g_err);
     if (log_on()) std::fprintf(stderr, "[stencil] error %d: %s\n", (int)st, buf);
     // a failed allocation leaves its error as the runtime's last error; clear
     // it so that a later launch check does not report it as a launch failure
@@ -462,7 +462,7 @@ hipError_t run_pre(stencil_plan_s *p, void *const *fields, hipStream_t s) {
 // saturated sweep at the same shape, so the last launch (the one that leaves
 // the residual partials) is always of the plan's form.
 hipError_t run_sweeps(stencil_plan_s *p, void *const *fields, SweepArgs a, int iterations, hipStream_t s,
-                      int *launches) {
+                      int *launches, double *part) {
     const bool wave = p->kind == STENCIL_WAVE25;
     const int eb = elem_bytes(p->dtype);
     void *src = wave ? fields[1] : fields[0], *dst = wave ? fields[0] : fields[1];
@@ -476,7 +476,7 @@ hipError_t run_sweeps(stencil_plan_s *p, void *const *fields, SweepArgs a, int i
         const int adv = sweeps_per_launch(v);
         a.src = src;
         a.dst = dst;
-        a.part = (t + adv == iterations) ? p->d_part : nullptr;
+        a.part = (t + adv == iterations) ? part : nullptr;
         if ((e = p->ops->launch(v, p->tile, a, s)) != hipSuccess) return e;
         t += adv;
         ++*launches;
@@ -509,7 +509,7 @@ hipError_t capture_run(stencil_plan_s *p, void *const *fields, const SweepArgs &
     for (int part = 0; part < 3 && e == hipSuccess; ++part) {
         if ((e = hipStreamBeginCapture(rg->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) break;
         const hipError_t le = part == 0 ? run_pre(p, fields, rg->cap)
-                              : part == 1 ? run_sweeps(p, fields, a, iterations, rg->cap, &launches)
+                              : part == 1 ? run_sweeps(p, fields, a, iterations, rg->cap, &launches, p->d_part)
                                           : run_post(p, fields, launches, rg->cap);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(rg->cap, &g);
@@ -626,7 +626,8 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
         if ((e = run_pre(p, fields, s)) != hipSuccess) return hip_fail(e, "halo copy launch");
         if (p->profiling && (e = hipEventRecord(p->ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         int launches = 0;
-        if ((e = run_sweeps(p, fields, a, iterations, s, &launches)) != hipSuccess) return hip_fail(e, "sweep launch");
+        if ((e = run_sweeps(p, fields, a, iterations, s, &launches, p->d_part)) != hipSuccess)
+            return hip_fail(e, "sweep launch");
         if (p->profiling) {
             if ((e = hipEventRecord(p->ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
             p->prof_sweeps = iterations;
@@ -635,6 +636,43 @@ stencil_status stencil_run(stencil_plan_t p, void *const *fields, const void *co
         if ((e = run_post(p, fields, launches, s)) != hipSuccess) return hip_fail(e, "tail copy launch");
     }
     p->has_resid = true;
+    return STENCIL_OK;
+}
+
+// The sweeps of stencil_run, eagerly, with the residual partials in the
+// library's device scratch and the reduced residual in the caller's memory.
+// Nothing is allocated: no HIP allocation, no host heap (errors are written
+// into a fixed thread-local buffer).
+stencil_status stencil_run_noalloc(stencil_plan_t p, void *const *fields, const void *const *coef_arrays,
+                                   int32_t iterations, double *residual_dev, void *stream_) {
+    if (!p) return fail(STENCIL_E_INVAL, "plan is NULL");
+    if (p->batch) return fail(STENCIL_E_UNSUPPORTED, "batched plans have no allocation-free run");
+    if (p->kind == STENCIL_GENERIC && p->variant == V_SATURATED && p->base_args.rtc)
+        return fail(STENCIL_E_UNSUPPORTED, "generated GENERIC kernels are looked up by their source text at launch; "
+                                           "the allocation-free run takes the table-driven kernel only");
+    if (p->nblocks > kNoallocPartials)
+        return fail(STENCIL_E_UNSUPPORTED, "the plan's sweep launch has %lld blocks; the allocation-free run holds at most %lld",
+                    p->nblocks, kNoallocPartials);
+    if (!fields) return fail(STENCIL_E_INVAL, "fields is NULL");
+    if (iterations < 0) return fail(STENCIL_E_INVAL, "iterations < 0");
+    if ((uintptr_t)residual_dev % alignof(double)) return fail(STENCIL_E_INVAL, "residual_dev is not 8-byte aligned");
+    SweepArgs a{};
+    stencil_status st = prepare_run_args(p, fields, coef_arrays, a);
+    if (st != STENCIL_OK) return st;
+    if (iterations == 0) return STENCIL_OK;
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return fail(STENCIL_E_DEVICE, "cannot make device %d current", p->device);
+    hipStream_t s = (hipStream_t)stream_;
+    hipError_t e;
+    double *scr = nullptr;
+    if ((e = noalloc_scratch(&scr)) != hipSuccess) return hip_fail(e, "device scratch address");
+    if ((e = run_pre(p, fields, s)) != hipSuccess) return hip_fail(e, "halo copy launch");
+    int launches = 0;
+    if ((e = run_sweeps(p, fields, a, iterations, s, &launches, scr)) != hipSuccess) return hip_fail(e, "sweep launch");
+    if ((e = run_post(p, fields, launches, s)) != hipSuccess) return hip_fail(e, "tail copy launch");
+    if (residual_dev &&
+        (e = launch_reduce_partials(scr, p->nblocks, scr + kNoallocPartials, residual_dev, s)) != hipSuccess)
+        return hip_fail(e, "reduce launch");
     return STENCIL_OK;
 }
 
@@ -786,7 +824,7 @@ stencil_status stencil_destroy(stencil_plan_t p) {
     return STENCIL_OK;
 }
 
-const char *stencil_last_error(void) { return g_err.c_str(); }
+const char *stencil_last_error(void) { return g_err; }
 
 const char *stencil_version(void) { return "0.1.0 gfx950"; }
 

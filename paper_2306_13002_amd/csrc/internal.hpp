@@ -90,6 +90,11 @@ hipError_t launch_interior_copy(const void *src, void *dst, int elem_bytes, cons
 // chunk of part[] into scratch[], then one block sums scratch[].
 constexpr int kReduceBlocks = 256;
 hipError_t launch_reduce_partials(const double *part, long long n, double *scratch, double *out, hipStream_t s);
+// Allocation-free run: a file-scope device array of kNoallocPartials residual
+// partials followed by kReduceBlocks first-pass sums.  noalloc_scratch gives
+// its address on the current device (looked up once per device, then cached).
+constexpr long long kNoallocPartials = 1LL << 17;
+hipError_t noalloc_scratch(double **out);
 // out[p] = sum of part[seg[p] .. seg[count+p]) in a fixed order, p < count.
 hipError_t launch_segment_sums(const double *part, const int *seg, int count, double *out, hipStream_t s);
 

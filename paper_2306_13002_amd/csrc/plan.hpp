@@ -92,6 +92,6 @@ stencil_status prepare_run_args(const stencil_plan_s *p, void *const *fields, co
                                 SweepArgs &a);
 hipError_t run_pre(stencil_plan_s *p, void *const *fields, hipStream_t s);
 hipError_t run_sweeps(stencil_plan_s *p, void *const *fields, SweepArgs a, int iterations, hipStream_t s,
-                      int *launches);
+                      int *launches, double *part);
 hipError_t run_post(stencil_plan_s *p, void *const *fields, int launches, hipStream_t s);
 }  // namespace stn

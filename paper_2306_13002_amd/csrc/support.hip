@@ -1,4 +1,7 @@
-// support.hip -- halo copy, periodic halo fill and the residual's final pass.
+// support.hip -- halo copy, periodic halo fill, the residual's final pass and
+// the device scratch of the allocation-free run.
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace stn {
@@ -174,6 +177,36 @@ hipError_t launch_reduce_partials(const double *part, long long n, double *scrat
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_pass1_kernel, dim3(1), dim3(256), 0, s, (const double *)scratch, nb, nb, out);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free run: kNoallocPartials per-block residual
+// partials, then kReduceBlocks first-pass sums of their reduction.  One copy
+// per GPU, resident until the process ends.  In host code the array's name
+// is not a device address: only the address hipGetSymbolAddress returns for
+// the current device is passed to kernels.
+static __device__ __align__(256) double scratch[kNoallocPartials + kReduceBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(double **out) {
+    *out = nullptr;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        double *ptr = nullptr;
+        if ((e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace stn

@@ -69,6 +69,7 @@ def lib():
         vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
         L.stencil_plan.argtypes = [ctypes.POINTER(StencilDesc), ctypes.POINTER(vp)]
         L.stencil_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
+        L.stencil_run_noalloc.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, vp]
         L.stencil_residual.argtypes = [vp, dp, vp]
         L.stencil_plan_config.argtypes = [vp] + [ctypes.POINTER(i32)] * 5
         L.stencil_plan_graph.argtypes = [vp, ctypes.POINTER(i32)]
@@ -88,7 +89,8 @@ def lib():
         L.stencil_prepare.restype = ctypes.c_int
         L.stencil_stream.argtypes = [i32, vp, vp, vp, vp, ctypes.c_int64, i32, i32, i32, vp]
         L.stencil_stream.restype = ctypes.c_int
-        for f in (L.stencil_plan, L.stencil_run, L.stencil_residual, L.stencil_plan_config, L.stencil_plan_graph,
+        for f in (L.stencil_plan, L.stencil_run, L.stencil_run_noalloc, L.stencil_residual, L.stencil_plan_config,
+                  L.stencil_plan_graph,
                   L.stencil_plan_use_graphs, L.stencil_batch_problem_config,
                   L.stencil_profile_enable, L.stencil_profile_read, L.stencil_destroy, L.stencil_plan_batch,
                   L.stencil_residuals, L.stencil_candidates, L.stencil_features, L.stencil_mlp_train,
@@ -243,6 +245,24 @@ class Plan(_GridLayout):
         current stream).  For wave25, returns (older, newer) tensors."""
         fp, cp = self._pointers(fields, coef_arrays)
         _check(lib().stencil_run(self._h, fp, cp, int(iterations), ctypes.c_void_p(_stream_handle(stream))))
+        if self.kind == "wave25":
+            return (fields[1], fields[0]) if iterations % 2 == 1 else (fields[0], fields[1])
+        return fields[0]
+
+    def run_noalloc(self, fields, coef_arrays=None, iterations: int = 1, residual=None, stream=None):
+        """stencil_run_noalloc: the sweeps of run() with the library's device
+        scratch; the FP64 residual goes to `residual` (a float64 device
+        tensor, element 0), or nowhere if None.  Never synchronizes."""
+        fp, cp = self._pointers(fields, coef_arrays)
+        import torch
+
+        rp = None
+        if residual is not None:
+            if residual.dtype != torch.float64 or not residual.is_cuda or residual.numel() < 1:
+                raise ValueError("residual must be a float64 device tensor with at least one element")
+            rp = ctypes.c_void_p(residual.data_ptr())
+        _check(lib().stencil_run_noalloc(self._h, fp, cp, int(iterations), rp,
+                                         ctypes.c_void_p(_stream_handle(stream))))
         if self.kind == "wave25":
             return (fields[1], fields[0]) if iterations % 2 == 1 else (fields[0], fields[1])
         return fields[0]
