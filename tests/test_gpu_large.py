@@ -220,18 +220,21 @@ def test_generic_plain_plane_pitch_beyond_int32_offsets(dev):
     assert abs(gr - wr) <= 1e-10 * wr
 
 
-def test_wave25_saturated_plane_limit(dev):
+@pytest.mark.parametrize("kind,kw,sat_forms", [("wave25", dict(coef=synth.WAVE25_COEF), ["saturated"])])
+def test_saturated_plane_limit(dev, kind, kw, sat_forms):
     # The saturated leapfrog kernel addresses a plane with 32-bit byte
-    # offsets: a plane pitch above 0xFFFFFFF0 bytes is refused for SATURATED
-    # and sends AUTO to PLAIN.  Only plans are made here (no grid is allocated).
+    # offsets: a plane pitch above 0xFFFFFFF0 bytes is refused for its
+    # saturated form and sends AUTO to PLAIN.  Only plans are made here (no
+    # grid is allocated).
     from paper_2306_13002_amd.stencil import E_UNSUPPORTED, Plan, StencilError
 
     n = (8, 8, 8)
     big, fits = 0xFFFFFFF0 // 8 + 1, 0xFFFFFFF0 // 8
-    with pytest.raises(StencilError) as e:
-        Plan("wave25", n, variant="saturated", coef=synth.WAVE25_COEF, pitch=(0, big))
-    assert e.value.status == E_UNSUPPORTED
-    with Plan("wave25", n, variant="auto", coef=synth.WAVE25_COEF, pitch=(0, big)) as p:
+    for v in sat_forms:
+        with pytest.raises(StencilError) as e:
+            Plan(kind, n, variant=v, pitch=(0, big), **kw)
+        assert e.value.status == E_UNSUPPORTED
+        with Plan(kind, n, variant=v, pitch=(0, fits), **kw) as p:
+            assert p.config()["variant"] == v
+    with Plan(kind, n, variant="auto", pitch=(0, big), **kw) as p:
         assert p.config()["variant"] == "plain"
-    with Plan("wave25", n, variant="saturated", coef=synth.WAVE25_COEF, pitch=(0, fits)) as p:
-        assert p.config()["variant"] == "saturated"
