@@ -113,10 +113,9 @@ typedef enum { STENCIL_F32 = 1, STENCIL_F64 = 2 } stencil_dtype; /* storage type
  * is recomputed on a one-cell ring around each tile so the second can follow
  * it plane by plane, and every input stream is read once per two sweeps.
  * Bit-identical to SATURATED at the same tile, z-block and tile map (an odd
- * sweep count starts with one SATURATED sweep).  EXHAUSTIVE tuning of AUTO
- * considers it beside PLAIN and SATURATED; the cost model (MODEL, and the
- * candidates stencil_candidates lists for AUTO) does not: it has no timings
- * of it. */
+ * sweep count starts with one SATURATED sweep).  EXHAUSTIVE and MODEL tuning
+ * of AUTO consider it beside PLAIN and SATURATED (the model's form feature
+ * tells the three apart; its target is the time per sweep in every form). */
 typedef enum {
     STENCIL_PLAIN = 0,
     STENCIL_SATURATED = 1,

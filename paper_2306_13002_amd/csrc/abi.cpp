@@ -364,8 +364,7 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     if (dv == STENCIL_SATURATED && !has_sat)
         return fail(STENCIL_E_UNSUPPORTED, "kind %d has no saturated form", p->kind);
     const bool open = !is_point_form(dv) && (dv == STENCIL_AUTO || !d->tile_x || !d->tile_y || !d->zblock || !d->tile_map);
-    // the cost model has no timings of the two-sweep form: it is tuned exhaustively
-    if (d->tune == STENCIL_TUNE_MODEL && open && dv != STENCIL_SATURATED_T2) {
+    if (d->tune == STENCIL_TUNE_MODEL && open) {
         TuneRequest rq{has_sat ? dv : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map};
         TuneEntry e{};
         stencil_status st = tune_model(p, rq, &e);

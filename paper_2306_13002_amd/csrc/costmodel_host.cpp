@@ -64,16 +64,21 @@ StencilInfo stencil_info(const stencil_desc *d, const Geom &g) {
 // Features of one (stencil, candidate):
 //  0 XCD-chunked tile map   1 radius            2 fraction of off-axis taps
 //  3 taps                   4 distinct coefs    5 bytes per element
-//  6-8 log2 nx, ny, nz      9 log2 points      10 saturated form
+//  6-8 log2 nx, ny, nz      9 log2 points      10 form: 0 plain, 1 saturated,
+//                                                 2 saturated, two sweeps per pass
 // 11-13 log2 tile x, y, z  14 read-footprint ratio of a tile incl. halo
 // 15 LDS bytes per block   16 estimated VGPRs  17 estimated waves per SIMD
-// 18 algorithmic bytes/pt  19 flops/pt of the form   20 arithmetic intensity
+// 18 algorithmic bytes per point and sweep (halved by two sweeps per pass)
+// 19 flops/pt of the form (two sweeps per pass: with the recomputed ring)
+// 20 arithmetic intensity
 // 21 the paper's static cost of the form's per-point expression (Sec. Cost
 //    Model: constants 0, inputs 1, operations 10, memory accesses 100)
 // 22 working set / 256 MB  23 blocks / 256 CUs
+// The target the model learns is log(seconds per sweep) in every form.
 void cost_features(const StencilInfo &si, const Cand &c, float out[24]) {
     const int r = si.r, tx = c.tile.tx, ty = c.tile.ty, tz = c.tile.tz;
-    const bool sat = c.variant == V_SATURATED;
+    const bool t2 = c.variant == V_SAT2;
+    const bool sat = c.variant == V_SATURATED || t2;
     const double pts = (double)si.g.nx * si.g.ny * si.g.nz;
     double bytes_pt, flops, loads, ops, inputs, lds = 0, vgpr, blocks;
     switch (si.kind) {
@@ -118,19 +123,32 @@ void cost_features(const StencilInfo &si, const Cand &c, float out[24]) {
         vgpr = sat ? 40 + 4.0 * (2 * r + 1) : 32;
     }
     }
+    // two sweeps per pass (POISSON19, HEAT3D7; radius 1): the state tile carries a
+    // two-cell ring and the first sweep is recomputed on a one-cell ring, four
+    // LDS planes of each; the bytes of one pass serve two sweeps
+    double ring1 = 1.0;
+    if (t2) {
+        ring1 = (double)(tx + 2) * (ty + 2) / ((double)tx * ty);
+        bytes_pt *= 0.5;
+        flops *= 0.5 * (1.0 + ring1);
+        const double eb = si.kind == STENCIL_POISSON19 ? 4 : 8;
+        lds = 4.0 * eb * ((ty + 4.0) * (tx + 5.0) + (ty + 2.0) * (tx + 3.0));
+        vgpr = si.kind == STENCIL_POISSON19 ? 158 : 56;
+    }
     blocks = std::ceil((double)si.g.nx / tx) * std::ceil((double)si.g.ny / ty) * std::ceil((double)si.g.nz / tz);
-    const double threads = (double)tx * ty * (sat ? 1 : tz);
+    const double threads = (double)tx * ty * (sat ? (t2 ? ring1 : 1.0) : tz);
     const double wpb = std::ceil(threads / 64);
     double waves = std::min(8.0, std::floor(512.0 / vgpr));
     if (lds > 0) waves = std::min(waves, std::floor(160.0 * 1024 / lds) * wpb / 4);
-    const double foot = sat ? (double)(tx + 2 * r) * (ty + 2 * r) / ((double)tx * ty)
+    const int rf = t2 ? 2 * r : r;
+    const double foot = sat ? (double)(tx + 2 * rf) * (ty + 2 * rf) / ((double)tx * ty)
                             : (double)(tx + 2 * r) * (ty + 2 * r) * (tz + 2 * r) / ((double)tx * ty * tz);
     const double ws = (si.kind == STENCIL_POISSON19 ? 14.0 * 4 : (si.kind == STENCIL_WAVE25 ? 3.0 * 8 : 2.0 * si.eb)) *
                       (si.g.nx + 2.0 * r) * (si.g.ny + 2.0 * r) * (si.g.nz + 2.0 * r);
     const double cost = 100.0 * (loads + 1) + 10.0 * ops + 1.0 * inputs;
     const double f[24] = {(double)(sat && c.remap), (double)r, si.box_frac, (double)si.n_taps, (double)si.n_coef,
                           (double)si.eb, std::log2((double)si.g.nx), std::log2((double)si.g.ny),
-                          std::log2((double)si.g.nz), std::log2(pts), (double)sat, std::log2((double)tx),
+                          std::log2((double)si.g.nz), std::log2(pts), t2 ? 2.0 : (double)sat, std::log2((double)tx),
                           std::log2((double)ty), std::log2((double)tz), foot, lds, vgpr, waves, bytes_pt, flops,
                           flops / bytes_pt, cost, ws / (256.0 * 1024 * 1024), blocks / 256.0};
     for (int i = 0; i < 24; ++i) out[i] = (float)f[i];
@@ -193,15 +211,10 @@ bool load_model(std::vector<float> &model) {
 
 }  // namespace
 
-// The cost model's candidates: the exhaustive tuner's, without the two-sweep
-// form unless it is asked for by name (the model's features describe only
-// the plain and single-sweep saturated forms, and its training campaign has
-// no timings of the two-sweep form).
+// The cost model's candidates: the exhaustive tuner's, the two-sweep form
+// included (feature 10 tells it apart, and the training campaign times it).
 std::vector<Cand> model_candidates(const KindOps *ops, int kind, const Geom &g, const TuneRequest &rq) {
-    std::vector<Cand> c = tune_candidates(ops, kind, g, rq);
-    if (rq.variant != V_SAT2)
-        c.erase(std::remove_if(c.begin(), c.end(), [](const Cand &x) { return x.variant == V_SAT2; }), c.end());
-    return c;
+    return tune_candidates(ops, kind, g, rq);
 }
 
 stencil_status tune_model(stencil_plan_s *p, const TuneRequest &rq, TuneEntry *best) {
@@ -260,7 +273,7 @@ stencil_status stencil_features(const stencil_desc *d, int32_t variant, int32_t 
     int rz = 0;
     stencil_status st = validate_desc(d, g, rz);
     if (st != STENCIL_OK) return st;
-    if ((variant != V_PLAIN && variant != V_SATURATED) || tile_x < 1 || tile_y < 1 || zblock < 1 ||
+    if ((variant != V_PLAIN && variant != V_SATURATED && variant != V_SAT2) || tile_x < 1 || tile_y < 1 || zblock < 1 ||
         (tile_map != 1 && tile_map != 2))
         return fail(STENCIL_E_INVAL, "bad candidate");
     cost_features(stencil_info(d, g), Cand{variant, Tile{tile_x, tile_y, zblock}, tile_map == 2}, out);
