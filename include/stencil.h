@@ -175,8 +175,8 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out);
  * shape open, by timing the class's own work-list kernel over all its
  * problems (on scratch grids the library allocates for the tuning and frees;
  * on E_NOMEM for those, by tuning its largest problem alone), else the
- * defaults or ds[0]'s fields -- and a persistent work-list kernel over
- * (problem, tile) items.  stencil_batch_problem_config reports each
+ * defaults or ds[0]'s fields -- and a work-list kernel over (problem,
+ * tile) items, one block per item.  stencil_batch_problem_config reports each
  * problem's class and shape.  stencil_run on a
  * batch plan takes fields = {p0.fields[0], p0.fields[1], p1.fields[0], ...}
  * and replays one hipGraph per (iterations, field pointers): halo copies, the

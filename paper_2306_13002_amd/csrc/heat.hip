@@ -309,9 +309,10 @@ __global__ __launch_bounds__((H3Sat2Shape<TX, TY>::NT)) void heat3d7_sat2(const 
     }
 }
 
-// Persistent work-list forms: each block walks items blockIdx.x, +gridDim.x,
-// ... and runs the same tile body as the single-problem kernel, so a batched
-// problem is bit-identical to its own run with the same form and shape.
+// Work-list forms: each block walks items blockIdx.x, +gridDim.x, ... (the
+// batch launches one block per item up to 2^20 items) and runs the same tile
+// body as the single-problem kernel, so a batched problem is bit-identical to
+// its own run with the same form and shape.
 template <int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void heat3d7_sat_batch(const BatchProb *__restrict__ probs,
                                                             const BatchItem *__restrict__ items, int n_items,
