@@ -113,7 +113,9 @@ typedef enum { STENCIL_F32 = 1, STENCIL_F64 = 2 } stencil_dtype; /* storage type
  * is recomputed on a one-cell ring around each tile so the second can follow
  * it plane by plane, and every input stream is read once per two sweeps.
  * Bit-identical to SATURATED at the same tile, z-block and tile map (an odd
- * sweep count starts with one SATURATED sweep).  EXHAUSTIVE and MODEL tuning
+ * sweep count starts with one SATURATED sweep).  POISSON19's two-sweep kernel
+ * addresses a plane with 32-bit byte offsets: pitch_z*4 above 0xFFFFFFF0
+ * bytes is E_UNSUPPORTED for SATURATED_T2, and the tuners leave the form out.  EXHAUSTIVE and MODEL tuning
  * of AUTO consider it beside PLAIN and SATURATED (the model's form feature
  * tells the three apart; its target is the time per sweep in every form). */
 typedef enum {

@@ -360,6 +360,9 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
         has_sat = false;
         if (dv == STENCIL_AUTO) dv = STENCIL_PLAIN;
     }
+    // so does the two-sweep Poisson kernel (the tuners leave it out above that)
+    if (p->kind == STENCIL_POISSON19 && dv == V_SAT2 && p->g.pz * (long long)sizeof(float) > kMaxPlaneBytes32)
+        return fail(STENCIL_E_UNSUPPORTED, "POISSON19 SATURATED_T2 needs pitch_z*4 <= %lld bytes", kMaxPlaneBytes32);
     if (d->tile_map < 0 || d->tile_map > 2) return fail(STENCIL_E_INVAL, "tile_map %d not in 0..2", d->tile_map);
     if (dv == STENCIL_SATURATED && !has_sat)
         return fail(STENCIL_E_UNSUPPORTED, "kind %d has no saturated form", p->kind);

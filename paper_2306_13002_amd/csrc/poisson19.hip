@@ -320,6 +320,15 @@ __device__ __forceinline__ ZTerms z_terms(const float *q, int e) {
     return ZTerms{q[e], (double)q[e + W] - (double)q[e - W], (double)q[e + 1] - (double)q[e - 1]};
 }
 
+// F32 access to one plane through a scalar buffer resource (plane_rsrc: the
+// base in 4 SGPRs, a 32-bit byte offset per lane; planes below 4 GiB).
+__device__ __forceinline__ float buf_ld_f32(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st_f32(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+
 // SATURATED, two sweeps per pass over memory (temporal blocking).  A block
 // owns a TX x TY output tile and streams z.  Sweep 1 is computed on the tile
 // plus a one-cell ring (its values are needed by sweep 2's neighbours and are
@@ -342,15 +351,13 @@ struct Sat2Shape {
     static constexpr int EY0 = (RS + TX - 1) / TX;
     static constexpr int EY = (TX * (TY + EY0)) % 64 == 0 ? EY0 : EY0 + 1;  // whole waves
     static constexpr int NT = TX * (TY + EY);
-    // the loop unrolled by the ring size (constant slot addresses) takes
-    // 10-20 more VGPRs: measured 5 % faster at 64 x 8, slower at the other
-    // shapes (lost occupancy, or spills at 896 threads)
-    static constexpr bool UNROLL = TX == 64 && TY == 8;
     // z-queues (each thread keeps the centre values and y-/x-differences of
     // the two planes below the one it reads): 19 -> 13 LDS reads and
-    // conversions per update; 26 more VGPRs, which only 64 x 8 absorbs
-    // without losing occupancy (26.2 -> 25.2 us per sweep there)
-    static constexpr bool ZQ = TX == 64 && TY == 8;
+    // conversions per update for about 20 more VGPRs.  Measured faster at
+    // 64 x 8, 128 x 4 and 32 x 4; at 64 x 4 (7 waves) they cost the second
+    // block per CU, and at 32 x 8 they measured slower at the z-blocks that
+    // matter (16, 32).
+    static constexpr bool ZQ = (TX == 64 && TY == 8) || (TX == 128 && TY == 4) || (TX == 32 && TY == 4);
 };
 
 template <int TX, int TY>
@@ -408,9 +415,10 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
 
     HaloStager<float, TX, TY, 2, true, NT> halo;
     halo.init(tid, bx * TX + 1, by * TY + 1, g.py, PX, PY);
+    constexpr int HR = decltype(halo)::HR;
 
     const int zlo = k0, zhi = k1 + 1;  // sweep-1 planes computed: zlo .. zhi (padded)
-    // prologue: p^t planes zlo-1 (if any) and zlo into LDS, zlo+1 into registers
+    // prologue: p^t planes zlo-1 (if any) and zlo into LDS
     for (int z = zlo - 1; z <= zlo; ++z) {
         if (z < 0) continue;
         const float *pl = p + (long long)z * g.pz;
@@ -418,20 +426,42 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
         halo.load(pl);
         halo.store(r0[(z - zlo + 4) & 3]);
     }
-    float ctr = ld_o ? p[col_o + (long long)(zlo + 1) * g.pz] : 0.0f;
-    halo.load(p + (long long)(zlo + 1) * g.pz);
-    // coefficients of this thread's sweep-1 cell for the plane about to be
-    // computed, and (tile threads) of the own cell for the two planes before
-    // it: sweep 2 runs two planes behind sweep 1
-    float cf[12], c1[12], c2[12];
+    // From here every load is unconditional and goes through a scalar buffer
+    // resource per plane with a 32-bit byte offset per lane (planes below
+    // 4 GiB, checked on the host).  A lane with nothing to load reads the
+    // cell of its own tile column (the tile's first row for ring threads),
+    // which the tile loads anyway, so the request coalesces with real ones;
+    // a cell outside the padded array reads the clamped cell of its row, a
+    // ring cell outside it is stored as 0, and a load for a plane the block
+    // does not need reads one it does.  None of those values is used.  No
+    // register is then merged with an older value or zeroed while a load
+    // into it is in flight.
+    const long long pzb = g.pz * (long long)sizeof(float);
+    auto cb = [&](int y, int x) -> unsigned {
+        return (unsigned)(((long long)min(max(y, 0), PY - 1) * g.py + min(max(x, 0), PX - 1)) * (long long)sizeof(float));
+    };
+    const unsigned ob = tile_t ? cb(yo, xo) : cb(by * TY + 1, xo);  // centre of p (own column)
+    const unsigned ab = has_r ? cb(yr, xr) : ob;                     // coefficients of the sweep-1 cell
+    unsigned hb[HR];
+#pragma unroll
+    for (int h = 0; h < HR; ++h) hb[h] = halo.ok[h] ? (unsigned)(halo.goff[h] * (long long)sizeof(float)) : ob;
+    auto ld = [](const void *plane, unsigned off) -> float { return buf_ld_f32(plane_rsrc(plane), off); };
+    float ctr = ld((const char *)p + (long long)(zlo + 1) * pzb, ob);
+    float hv[HR];
+#pragma unroll
+    for (int h = 0; h < HR; ++h) hv[h] = ld((const char *)p + (long long)(zlo + 1) * pzb, hb[h]);
+    // Coefficients of this thread's sweep-1 cell, in four sets, one per plane
+    // mod 4: set P = (zA - zlo) mod 4 is loaded at step zA (plane zA+1), read
+    // by sweep 1 at step zA+1 and (tile threads: the own cell) by sweep 2 at
+    // step zA+3, two planes behind, and reloaded at step zA+4, so no set is
+    // ever copied.  Set 3 starts with plane zlo.
+    float cf[4][12];
     {
-        const bool zin = zlo >= 1 && zlo <= g.nz;
-        const long long qa = col_a + (long long)zlo * g.pz;
+        const long long zo = (long long)max(zlo, 1) * pzb;
 #pragma unroll
         for (int s = 0; s < 12; ++s) {
-            cf[s] = (zin && in_a) ? c.f[s][qa] : 0.0f;
-            c1[s] = 0.0f;
-            c2[s] = 0.0f;
+            cf[0][s] = cf[1][s] = cf[2][s] = 0.0f;
+            cf[3][s] = ld((const char *)c.f[s] + zo, ab);
         }
     }
     // z-queues: the terms of planes zA-1 and zA for sweep 1 (from the p^t
@@ -451,28 +481,32 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
     // barrier per plane separates every LDS write from its readers.  Ring
     // slots are relative to zlo: plane z sits in slot (z - zlo) mod 4; SM,
     // S0, SP, S2 are the slots of planes zA-1, zA, zA+1 and zA+2 (= zA-2).
-    // running plane offsets (one 64-bit add per plane instead of a multiply per access)
-    const float *pl_next = p + (long long)(zlo + 2) * g.pz;
-    long long qz = (long long)(zlo + 1) * g.pz;   // plane zA+1, the coefficients loaded at step zA
-    float *out_pl = pn + (long long)(zlo - 2) * g.pz;  // plane zc = zA-2
-    auto step = [&](const int zA, const int SM, const int S0, const int SP, const int S2) {
-        float cc[12];
-#pragma unroll
-        for (int s = 0; s < 12; ++s) cc[s] = cf[s];
+    // running byte offsets of planes zA+2 (p), zA+1 (coefficients) and zA-2 (output)
+    // (clamped to the last plane each stream needs: the loads of the last
+    // steps re-read a plane just read, from L2)
+    long long o_p = (long long)(zlo + 2) * pzb, o_c = (long long)(zlo + 1) * pzb;
+    const long long p_max = (long long)min(zhi + 1, g.nz + 1) * pzb, c_max = (long long)min(zhi, g.nz) * pzb;
+    char *out_pl = (char *)pn + (long long)(zlo - 2) * pzb;
+    auto step = [&](const int zA, const int P, const int SM, const int S0, const int SP, const int S2) {
+        // the coefficients of plane zA (sweep 1) and of plane zA-2 (sweep 2)
+        const float *cc = cf[(P + 3) & 3], *cs = cf[(P + 1) & 3];
         if (zA <= zhi) {
-            // stage p^t plane zA+1, then issue every load of the next plane
+            // stage p^t plane zA+1
             if (tile_t) r0[SP][e0_o] = ctr;
-            halo.store(r0[SP]);
-            if (zA < zhi) {
-                if (zA + 2 <= g.nz + 1) {
-                    ctr = ld_o ? pl_next[col_o] : 0.0f;
-                    halo.load(pl_next);
-                }
-                const bool zin = zA + 1 >= 1 && zA + 1 <= g.nz;
-                const long long qa = col_a + qz;
 #pragma unroll
-                for (int s = 0; s < 12; ++s) cf[s] = (zin && in_a) ? c.f[s][qa] : 0.0f;
-            }
+            for (int h = 0; h < HR; ++h)
+                if (halo.has[h]) r0[SP][halo.lidx[h]] = halo.ok[h] ? hv[h] : 0.0f;
+        }
+        {
+            // every load of the next plane: p^t plane zA+2 (needed if zA < zhi and
+            // inside the array) and the coefficients of plane zA+1 (if interior)
+            const long long op = min(o_p, p_max);
+            ctr = ld((const char *)p + op, ob);
+#pragma unroll
+            for (int h = 0; h < HR; ++h) hv[h] = ld((const char *)p + op, hb[h]);
+            const long long oc = max(min(o_c, c_max), pzb);
+#pragma unroll
+            for (int s = 0; s < 12; ++s) cf[P][s] = ld((const char *)c.f[s] + oc, ab);
         }
         __syncthreads();
         const int zc = zA - 2;  // sweep 2 at plane zc, from sweep-1 planes zc-1 .. zc+1
@@ -493,8 +527,8 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
                 if (zc >= k0 + 1 && in_o) {
                     float v;
                     const double ss = p19_update_zq<W1>(r1[S2], e1_o, q2o.c, t.c, q2m.c, t.dy - q2m.dy,
-                                                        t.dx - q2m.dx, c2, omega, &v);
-                    out_pl[col_o] = v;
+                                                        t.dx - q2m.dx, cs, omega, &v);
+                    buf_st_f32(plane_rsrc(out_pl), ob, v);
                     acc = fma(ss, ss, acc);
                 }
                 q2m = q2o;
@@ -512,32 +546,28 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
             if (zc >= k0 + 1 && in_o) {
                 const float *m = r1[SP], *o = r1[S2], *u = r1[SM];
                 float v;
-                const double ss = p19_update<W1>(m, o, u, e1_o, c2, omega, &v);
-                out_pl[col_o] = v;
+                const double ss = p19_update<W1>(m, o, u, e1_o, cs, omega, &v);
+                buf_st_f32(plane_rsrc(out_pl), ob, v);
                 acc = fma(ss, ss, acc);
             }
         }
-#pragma unroll
-        for (int s = 0; s < 12; ++s) {
-            c2[s] = c1[s];
-            c1[s] = cc[s];
-        }
-        pl_next += g.pz;
-        qz += g.pz;
-        out_pl += g.pz;
+        o_p += pzb;
+        o_c += pzb;
+        out_pl += pzb;
     };
-    if (S::UNROLL) {  // four planes per trip: every slot a compile-time constant
-        for (int zA = zlo; zA <= zhi + 1; zA += 4) {
-            step(zA, 3, 0, 1, 2);
-            if (zA + 1 <= zhi + 1) step(zA + 1, 0, 1, 2, 3);
-            if (zA + 2 <= zhi + 1) step(zA + 2, 1, 2, 3, 0);
-            if (zA + 3 <= zhi + 1) step(zA + 3, 2, 3, 0, 1);
-        }
-    } else {
-        for (int zA = zlo; zA <= zhi + 1; ++zA) {
-            const int q = (zA - zlo) & 3;
-            step(zA, (q + 3) & 3, q, (q + 1) & 3, (q + 2) & 3);
-        }
+    // Four planes per trip: every ring slot and coefficient set is a
+    // compile-time constant.  The loop leaves between steps, so no step is
+    // skipped inside a trip and no value merges there (a merge would copy
+    // registers whose loads are still in flight, and wait for them).
+    for (int zA = zlo;; zA += 4) {
+        if (zA > zhi + 1) break;
+        step(zA, 0, 3, 0, 1, 2);
+        if (zA + 1 > zhi + 1) break;
+        step(zA + 1, 1, 0, 1, 2, 3);
+        if (zA + 2 > zhi + 1) break;
+        step(zA + 2, 2, 1, 2, 3, 0);
+        if (zA + 3 > zhi + 1) break;
+        step(zA + 3, 3, 2, 3, 0, 1);
     }
     if (part) {
         const double s = block_sum_f64(acc, red);

@@ -87,7 +87,9 @@ std::vector<Cand> tune_candidates(const KindOps *ops, int kind, const Geom &g, c
     if (want_v(V_PLAIN))
         for (const Tile &t : kPlainTiles)
             if (ops->tile_ok(V_PLAIN, t) && tile_fits(t)) out.push_back({V_PLAIN, t, 0});
-    if ((rq.variant == V_SAT2 || rq.variant == STENCIL_AUTO) && ops->sat2_tiles) {
+    // the two-sweep Poisson kernel addresses a plane with 32-bit byte offsets
+    const bool sat2_fits = kind != STENCIL_POISSON19 || g.pz * (long long)sizeof(float) <= kMaxPlaneBytes32;
+    if ((rq.variant == V_SAT2 || rq.variant == STENCIL_AUTO) && ops->sat2_tiles && sat2_fits) {
         Tile st[64];
         const int ns = ops->sat2_tiles(st, 64);
         std::vector<int> zbs;

@@ -220,21 +220,24 @@ def test_generic_plain_plane_pitch_beyond_int32_offsets(dev):
     assert abs(gr - wr) <= 1e-10 * wr
 
 
-@pytest.mark.parametrize("kind,kw,sat_forms", [("wave25", dict(coef=synth.WAVE25_COEF), ["saturated"])])
-def test_saturated_plane_limit(dev, kind, kw, sat_forms):
-    # The saturated leapfrog kernel addresses a plane with 32-bit byte
-    # offsets: a plane pitch above 0xFFFFFFF0 bytes is refused for its
-    # saturated form and sends AUTO to PLAIN.  Only plans are made here (no
-    # grid is allocated).
+@pytest.mark.parametrize("kind,kw,eb,form,auto_pick", [
+    ("wave25", dict(coef=synth.WAVE25_COEF), 8, "saturated", "plain"),
+    ("poisson19", dict(omega=0.8), 4, "saturated_t2", "saturated"),
+])
+def test_saturated_plane_limit(dev, kind, kw, eb, form, auto_pick):
+    # The saturated leapfrog kernel and the two-sweep Poisson kernel address a
+    # plane with 32-bit byte offsets: a plane pitch above 0xFFFFFFF0 bytes is
+    # refused for that form, and AUTO picks another (PLAIN for the leapfrog,
+    # the single-sweep SATURATED form for Poisson).  Only plans are made here
+    # (no grid is allocated).
     from paper_2306_13002_amd.stencil import E_UNSUPPORTED, Plan, StencilError
 
     n = (8, 8, 8)
-    big, fits = 0xFFFFFFF0 // 8 + 1, 0xFFFFFFF0 // 8
-    for v in sat_forms:
-        with pytest.raises(StencilError) as e:
-            Plan(kind, n, variant=v, pitch=(0, big), **kw)
-        assert e.value.status == E_UNSUPPORTED
-        with Plan(kind, n, variant=v, pitch=(0, fits), **kw) as p:
-            assert p.config()["variant"] == v
+    big, fits = 0xFFFFFFF0 // eb + 1, 0xFFFFFFF0 // eb
+    with pytest.raises(StencilError) as e:
+        Plan(kind, n, variant=form, pitch=(0, big), **kw)
+    assert e.value.status == E_UNSUPPORTED
+    with Plan(kind, n, variant=form, pitch=(0, fits), **kw) as p:
+        assert p.config()["variant"] == form
     with Plan(kind, n, variant="auto", pitch=(0, big), **kw) as p:
-        assert p.config()["variant"] == "plain"
+        assert p.config()["variant"] == auto_pick
