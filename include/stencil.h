@@ -75,6 +75,9 @@ typedef enum {
  *                + b2*(p(i+1,j,k+1) - p(i-1,j,k+1) - p(i+1,j,k-1) + p(i-1,j,k-1))
  *                + c0*p(i-1,j,k) + c1*p(i,j-1,k) + c2*p(i,j,k-1) + wrk1
  *             ss = (s0*a3 - p)*bnd ;  p' = p + omega*ss ;  residual = sum ss^2.
+ *           Its saturated kernels (SATURATED, SATURATED_T2) address a plane
+ *           with 32-bit byte offsets: pitch_z*4 above 0xFFFFFFF0 bytes is
+ *           E_UNSUPPORTED for them and makes AUTO choose PLAIN.
  * WAVE25    radius-4 star, second order in time (leapfrog), F64, r = 4:
  *             L(u) = sum over x,y,z of [c0*u + sum_{q=1..4} c_q*(u(+q) + u(-q))]
  *             u_next = 2u - u_prev + vsq*L(u);   coef = {c0,c1,c2,c3,c4}.
@@ -113,9 +116,7 @@ typedef enum { STENCIL_F32 = 1, STENCIL_F64 = 2 } stencil_dtype; /* storage type
  * is recomputed on a one-cell ring around each tile so the second can follow
  * it plane by plane, and every input stream is read once per two sweeps.
  * Bit-identical to SATURATED at the same tile, z-block and tile map (an odd
- * sweep count starts with one SATURATED sweep).  POISSON19's two-sweep kernel
- * addresses a plane with 32-bit byte offsets: pitch_z*4 above 0xFFFFFFF0
- * bytes is E_UNSUPPORTED for SATURATED_T2, and the tuners leave the form out.  EXHAUSTIVE and MODEL tuning
+ * sweep count starts with one SATURATED sweep).  EXHAUSTIVE and MODEL tuning
  * of AUTO consider it beside PLAIN and SATURATED (the model's form feature
  * tells the three apart; its target is the time per sweep in every form). */
 typedef enum {

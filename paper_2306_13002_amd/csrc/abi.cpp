@@ -352,17 +352,17 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     const KindOps *ops = p->ops;
     bool has_sat = ops->sat_tiles != nullptr;
     int dv = d->variant;
-    // the saturated leapfrog kernel addresses a plane with 32-bit byte offsets
-    if (p->kind == STENCIL_WAVE25 && p->g.pz * (long long)sizeof(double) > kMaxPlaneBytes32) {
-        if (dv == STENCIL_SATURATED)
-            return fail(STENCIL_E_UNSUPPORTED, "WAVE25 SATURATED needs pitch_z*8 <= %lld bytes (PLAIN takes any plane)",
-                        kMaxPlaneBytes32);
+    // the saturated WAVE25 and POISSON19 kernels address a plane with 32-bit
+    // byte offsets
+    const long long plane_bytes = p->g.pz * (long long)elem_bytes(p->dtype);
+    if ((p->kind == STENCIL_WAVE25 || p->kind == STENCIL_POISSON19) && plane_bytes > kMaxPlaneBytes32) {
+        if (dv == STENCIL_SATURATED || dv == V_SAT2)
+            return fail(STENCIL_E_UNSUPPORTED,
+                        "kind %d: the saturated forms need pitch_z*%d <= %lld bytes (PLAIN takes any plane)", p->kind,
+                        elem_bytes(p->dtype), kMaxPlaneBytes32);
         has_sat = false;
         if (dv == STENCIL_AUTO) dv = STENCIL_PLAIN;
     }
-    // so does the two-sweep Poisson kernel (the tuners leave it out above that)
-    if (p->kind == STENCIL_POISSON19 && dv == V_SAT2 && p->g.pz * (long long)sizeof(float) > kMaxPlaneBytes32)
-        return fail(STENCIL_E_UNSUPPORTED, "POISSON19 SATURATED_T2 needs pitch_z*4 <= %lld bytes", kMaxPlaneBytes32);
     if (d->tile_map < 0 || d->tile_map > 2) return fail(STENCIL_E_INVAL, "tile_map %d not in 0..2", d->tile_map);
     if (dv == STENCIL_SATURATED && !has_sat)
         return fail(STENCIL_E_UNSUPPORTED, "kind %d has no saturated form", p->kind);

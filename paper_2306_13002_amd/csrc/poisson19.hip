@@ -172,6 +172,15 @@ __global__ void poisson19_point(const float *__restrict__ p, float *__restrict__
     }
 }
 
+// F32 access to one plane through a scalar buffer resource (plane_rsrc: the
+// base in 4 SGPRs, a 32-bit byte offset per lane; planes below 4 GiB).
+__device__ __forceinline__ float buf_ld_f32(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st_f32(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+
 template <int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void poisson19_sat(const float *__restrict__ p, float *__restrict__ pn,
                                                         P19Coef c, Geom g, double omega, int zb, int remap,
@@ -193,45 +202,72 @@ __global__ __launch_bounds__(TX *TY) void poisson19_sat(const float *__restrict_
 
     HaloStager<float, TX, TY, R, true, NT> halo;
     halo.init(tid, bx * TX + R, by * TY + R, g.py, PX, PY);
+    constexpr int HR = decltype(halo)::HR;
 
-    // prologue: planes zc0-1 and zc0 (zc = k + 1) into the ring
+    // prologue: planes zc0-1 and zc0 (zc = k + 1) into ring slots 0 and 1
+    // (plane z sits in slot (z - k0) mod 4)
     for (int z = k0; z <= k0 + 1; ++z) {
         const float *pl = p + (long long)z * g.pz;
-        ring[z & 3][me] = ld ? pl[col] : 0.0f;
+        ring[z - k0][me] = ld ? pl[col] : 0.0f;
         halo.load(pl);
-        halo.store(ring[z & 3]);
+        halo.store(ring[z - k0]);
     }
-    // registers for the plane after: p(zc+1) tile and coefficients at zc
-    float ctr = ld ? p[col + (long long)(k0 + 2) * g.pz] : 0.0f;
-    halo.load(p + (long long)(k0 + 2) * g.pz);
-    float cf[12];
-    {
-        const long long q = col + (long long)(k0 + 1) * g.pz;
+    // From here every load is unconditional and goes through a scalar buffer
+    // resource per plane with a 32-bit byte offset per lane (planes below
+    // 4 GiB, checked on the host): a lane with nothing to load reads the cell
+    // of its own column (clamped into the padded array), which the tile loads
+    // anyway; a ring cell outside the array is staged as 0; a load for a plane
+    // the block does not need re-reads the last one it did.  None of those
+    // values is used.
+    const long long pzb = g.pz * (long long)sizeof(float);
+    const unsigned ob =
+        (unsigned)(((long long)min(yp, PY - 1) * g.py + min(xp, PX - 1)) * (long long)sizeof(float));
+    unsigned hb[HR];
 #pragma unroll
-        for (int s = 0; s < 12; ++s) cf[s] = in ? c.f[s][q] : 0.0f;
+    for (int h = 0; h < HR; ++h) hb[h] = halo.ok[h] ? (unsigned)(halo.goff[h] * (long long)sizeof(float)) : ob;
+    auto ldb = [](const void *plane, unsigned off) -> float { return buf_ld_f32(plane_rsrc(plane), off); };
+    // registers for the plane after: p(zc+1) tile and the coefficients at zc,
+    // in two sets by the parity of k - k0: set P is loaded at step k (plane
+    // zc+1) and read at step k+1, so no set is ever copied
+    float ctr = ldb((const char *)p + (long long)(k0 + 2) * pzb, ob);
+    float hv[HR];
+#pragma unroll
+    for (int h = 0; h < HR; ++h) hv[h] = ldb((const char *)p + (long long)(k0 + 2) * pzb, hb[h]);
+    float cf[2][12];
+#pragma unroll
+    for (int s = 0; s < 12; ++s) {
+        cf[0][s] = 0.0f;
+        cf[1][s] = ldb((const char *)c.f[s] + (long long)(k0 + 1) * pzb, ob);
     }
     double acc = 0.0;
+    // running byte offsets of p plane zc+2 and coefficient plane zc+1, clamped
+    // to the last plane each stream needs
+    long long o_p = (long long)(k0 + 3) * pzb, o_c = (long long)(k0 + 2) * pzb;
+    const long long p_max = (long long)(k1 + 1) * pzb, c_max = (long long)k1 * pzb;
+    char *out_pl = (char *)pn + (long long)(k0 + 1) * pzb;
 
-    for (int k = k0; k < k1; ++k) {
-        const int zc = k + 1;
+    // step k: plane zc = k + 1; M, O, U are the slots of planes zc-1, zc,
+    // zc+1 and P the coefficient set loaded at this step
+    auto step = [&](const int P, const int M, const int O, const int U) {
         // stage plane zc+1
-        ring[(zc + 1) & 3][me] = ctr;
-        halo.store(ring[(zc + 1) & 3]);
-        // keep this plane's coefficients, then bulk-issue every load of the next plane
-        float cc[12];
+        ring[U][me] = ctr;
 #pragma unroll
-        for (int s = 0; s < 12; ++s) cc[s] = cf[s];
-        if (k + 1 < k1) {
-            const long long qn = col + (long long)(zc + 1) * g.pz;
+        for (int h = 0; h < HR; ++h)
+            if (halo.has[h]) ring[U][halo.lidx[h]] = halo.ok[h] ? hv[h] : 0.0f;
+        // bulk-issue every load of the next plane
+        {
+            const char *pl = (const char *)p + min(o_p, p_max);
+            ctr = ldb(pl, ob);
 #pragma unroll
-            for (int s = 0; s < 12; ++s) cf[s] = in ? c.f[s][qn] : 0.0f;
-            const float *pl = p + (long long)(zc + 2) * g.pz;
-            ctr = ld ? pl[col] : 0.0f;
-            halo.load(pl);
+            for (int h = 0; h < HR; ++h) hv[h] = ldb(pl, hb[h]);
+            const long long oc = min(o_c, c_max);
+#pragma unroll
+            for (int s = 0; s < 12; ++s) cf[P][s] = ldb((const char *)c.f[s] + oc, ob);
         }
+        const float *cc = cf[1 - P];
         __syncthreads();
         if (in) {
-            const float *m = ring[(zc - 1) & 3], *o = ring[zc & 3], *u = ring[(zc + 1) & 3];
+            const float *m = ring[M], *o = ring[O], *u = ring[U];
             const double pc = o[me];
             const double pE = o[me + 1], pW = o[me - 1], pN = o[me + W], pS = o[me - W];
             const double B0v = ((double)o[me + W + 1] - (double)o[me - W + 1]) -
@@ -249,9 +285,25 @@ __global__ __launch_bounds__(TX *TY) void poisson19_sat(const float *__restrict_
             s0 = fma((double)cc[A2], pU, s0);
             s0 = fma((double)cc[C2], pD, s0);
             const double ss = fma(s0, (double)cc[A3], -pc) * (double)cc[BND];
-            pn[col + (long long)zc * g.pz] = (float)fma(omega, ss, pc);
+            buf_st_f32(plane_rsrc(out_pl), ob, (float)fma(omega, ss, pc));
             acc = fma(ss, ss, acc);
         }
+        o_p += pzb;
+        o_c += pzb;
+        out_pl += pzb;
+    };
+    // Four planes per trip, so that every ring slot and coefficient set is a
+    // compile-time constant; the loop leaves between steps, so no step is
+    // skipped inside a trip and no value merges there.
+    for (int k = k0;; k += 4) {
+        if (k >= k1) break;
+        step(0, 0, 1, 2);
+        if (k + 1 >= k1) break;
+        step(1, 1, 2, 3);
+        if (k + 2 >= k1) break;
+        step(0, 2, 3, 0);
+        if (k + 3 >= k1) break;
+        step(1, 3, 0, 1);
     }
     if (part) {
         const double s = block_sum_f64(acc, red);
@@ -318,15 +370,6 @@ struct ZTerms {
 template <int W>
 __device__ __forceinline__ ZTerms z_terms(const float *q, int e) {
     return ZTerms{q[e], (double)q[e + W] - (double)q[e - W], (double)q[e + 1] - (double)q[e - 1]};
-}
-
-// F32 access to one plane through a scalar buffer resource (plane_rsrc: the
-// base in 4 SGPRs, a 32-bit byte offset per lane; planes below 4 GiB).
-__device__ __forceinline__ float buf_ld_f32(__amdgpu_buffer_rsrc_t r, unsigned off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-__device__ __forceinline__ void buf_st_f32(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
 
 // SATURATED, two sweeps per pass over memory (temporal blocking).  A block
@@ -405,12 +448,10 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
     }
     const int xr = bx * TX + ex, yr = by * TY + ey;  // padded
     const bool in_r = has_r && xr >= 1 && xr <= g.nx && yr >= 1 && yr <= g.ny;
-    const long long col_r = (long long)yr * g.py + xr;
     const int e0_r = (ey + 1) * W0 + ex + 1, e1_r = ey * W1 + ex;
     // the cell this thread computes in sweep 1
     const bool in_a = tile_t ? in_o : in_r;
     const bool has_a = tile_t || has_r;
-    const long long col_a = tile_t ? col_o : col_r;
     const int e0_a = tile_t ? e0_o : e0_r, e1_a = tile_t ? e1_o : e1_r;
 
     HaloStager<float, TX, TY, 2, true, NT> halo;
