@@ -181,8 +181,8 @@ def tuner_gap(out_path=None):
     weighs the two-sweep form (poisson19 129x129x257, heat3d7 160^3 and
     400^3; AUTO form): each plan's chosen configuration is timed the same
     way (median of 5 runs of 4 sweeps, HIP events) and the ratio reported.
-    The model predicts only the forms its features describe (plain and
-    single-sweep saturated), so this is the price of its blind spot."""
+    Both tuners weigh all three forms (the model tells them apart by its
+    form feature)."""
     import torch
     dev = torch.device("cuda:0")
     rows = []
