@@ -527,7 +527,7 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
     // steps re-read a plane just read, from L2)
     long long o_p = (long long)(zlo + 2) * pzb, o_c = (long long)(zlo + 1) * pzb;
     const long long p_max = (long long)min(zhi + 1, g.nz + 1) * pzb, c_max = (long long)min(zhi, g.nz) * pzb;
-    char *out_pl = (char *)pn + (long long)(zlo - 2) * pzb;
+    long long o_out = (long long)(zlo - 2) * pzb;  // >= pzb whenever a store happens
     auto step = [&](const int zA, const int P, const int SM, const int S0, const int SP, const int S2) {
         // the coefficients of plane zA (sweep 1) and of plane zA-2 (sweep 2)
         const float *cc = cf[(P + 3) & 3], *cs = cf[(P + 1) & 3];
@@ -569,7 +569,7 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
                     float v;
                     const double ss = p19_update_zq<W1>(r1[S2], e1_o, q2o.c, t.c, q2m.c, t.dy - q2m.dy,
                                                         t.dx - q2m.dx, cs, omega, &v);
-                    buf_st_f32(plane_rsrc(out_pl), ob, v);
+                    buf_st_f32(plane_rsrc((char *)pn + o_out), ob, v);
                     acc = fma(ss, ss, acc);
                 }
                 q2m = q2o;
@@ -588,13 +588,13 @@ __global__ __launch_bounds__((Sat2Shape<TX, TY>::NT)) void poisson19_sat2(const 
                 const float *m = r1[SP], *o = r1[S2], *u = r1[SM];
                 float v;
                 const double ss = p19_update<W1>(m, o, u, e1_o, cs, omega, &v);
-                buf_st_f32(plane_rsrc(out_pl), ob, v);
+                buf_st_f32(plane_rsrc((char *)pn + o_out), ob, v);
                 acc = fma(ss, ss, acc);
             }
         }
         o_p += pzb;
         o_c += pzb;
-        out_pl += pzb;
+        o_out += pzb;
     };
     // Four planes per trip: every ring slot and coefficient set is a
     // compile-time constant.  The loop leaves between steps, so no step is
