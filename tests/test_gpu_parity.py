@@ -391,8 +391,8 @@ def test_zero_iterations_and_state(dev):
     p.close()
 
 
-@pytest.mark.parametrize("kind", ["heat3d7", "wave25"])
-@pytest.mark.parametrize("variant", ["plain", "saturated"])
+@pytest.mark.parametrize("kind,variant", [("heat3d7", "plain"), ("heat3d7", "saturated"), ("heat3d7", "saturated_t2"),
+                                          ("wave25", "plain"), ("wave25", "saturated")])
 def test_pitched_layout(dev, kind, variant):
     # rows and planes padded beyond the grid: same result, gaps untouched
     n = (37, 13, 11)
@@ -433,6 +433,57 @@ def test_pitched_layout(dev, kind, variant):
         p.run(f, [_dev(pitched(v), dev)], iterations=3)
         buf = f[0].cpu().numpy()
         assert maxrel(inner(unpitched(buf), 4), inner(A, 4)) <= (0 if variant == "plain" else 1e-12)
+    mask = np.ones(PZ * pz, bool)
+    for z in range(PZ):
+        for y in range(PY):
+            mask[z * pz + y * py: z * pz + y * py + PX] = False
+    assert np.all(buf[mask] == -7.0)
+
+
+@pytest.mark.parametrize("variant,tile", [("plain", (64, 4, 1)), ("saturated", (64, 8, 4)), ("saturated", (128, 4, 64)),
+                                          ("saturated_t2", (64, 8, 4)), ("saturated_t2", (128, 4, 64)),
+                                          ("saturated_t2", (32, 8, 3))])
+def test_pitched_layout_poisson19(dev, variant, tile):
+    # p and all 12 coefficient grids with rows and planes padded beyond the
+    # grid (the saturated kernels address cells by byte offsets built from the
+    # pitches): plain equals the F32-store oracle bit for bit, the saturated
+    # forms equal their own unpitched runs bit for bit, and the gaps of the
+    # state grid are left alone
+    n = (37, 13, 11)
+    PX, PY, PZ = n[0] + 2, n[1] + 2, n[2] + 2
+    py, pz = PX + 7, (PX + 7) * PY + 19
+    p0, cf = synth.poisson19_random_inputs((PZ, PY, PX), seed=12)
+    T = 3
+
+    def pitched(g):
+        buf = np.full(PZ * pz, -7.0, dtype=np.float32)
+        for z in range(PZ):
+            for y in range(PY):
+                buf[z * pz + y * py: z * pz + y * py + PX] = g[z, y]
+        return buf
+
+    def unpitched(buf):
+        out = np.empty((PZ, PY, PX), dtype=np.float32)
+        for z in range(PZ):
+            for y in range(PY):
+                out[z, y] = buf[z * pz + y * py: z * pz + y * py + PX]
+        return out
+
+    p = Plan("poisson19", n, variant=variant, tile=tile, omega=0.8, pitch=(py, pz))
+    f = [_dev(pitched(p0), dev), torch.full((PZ * pz,), float("nan"), dtype=torch.float32, device=dev)]
+    p.run(f, [_dev(pitched(c), dev) for c in cf], iterations=T)
+    gg = p.residual()
+    p.close()
+    buf = f[0].cpu().numpy()
+    got = unpitched(buf)
+    if variant == "plain":
+        want, wg = oracle.poisson19(p0, cf, 0.8, T, mode="F32STORE")
+        assert np.array_equal(got.astype(np.float64), want)
+        assert abs(gg - wg) <= 1e-10 * wg
+    else:
+        ref, gr = run_jacobi("poisson19", p0, n, dev, T, coefs=cf, variant=variant, tile=tile, omega=0.8)
+        assert np.array_equal(got, ref)
+        assert gg == gr
     mask = np.ones(PZ * pz, bool)
     for z in range(PZ):
         for y in range(PY):
