@@ -64,6 +64,13 @@ typedef enum {
  * HEAT2D5   dst = c[0]*u + c[1]*u(-x) + c[1]*u(+x) + c[1]*u(-y) + c[1]*u(+y);
  *           r = 1, F64; coef = {centre, neighbour}.  Jacobi heat sweep, the
  *           paper's Jacobi class ("ostencil" in its SPEC ACCEL table).
+ *           PLAIN with zblock k > 1 (Dirichlet only) fuses up to k sweeps per
+ *           launch: each block loads its output tile and a k-cell ring into
+ *           LDS and runs the sweeps there (the ring recomputed by every block
+ *           that needs it), with the plain body's operands and order, so the
+ *           grid equals k single-sweep launches bit for bit (the residual is
+ *           the same sum taken in another order).  A run of T sweeps makes
+ *           ceil(T/k) launches, the first doing T mod k when that is not 0.
  * HEAT3D7   the same with -z, +z added; r = 1, F64.
  * POISSON19 19-point variable-coefficient pressure relaxation (the halo-3D
  *           CFD class of the paper's NPB/SPEC tables), F32 storage, FP64
@@ -157,7 +164,9 @@ typedef struct {
     double omega;           /* POISSON19 relaxation factor */
     int32_t tile_x;         /* threads along x per block; 0 = let the plan decide */
     int32_t tile_y;         /* rows per block tile; 0 = let the plan decide */
-    int32_t zblock;         /* z planes per block (saturated forms); 0 = let the plan decide */
+    int32_t zblock;         /* z planes per block (saturated forms); 0 = let the plan decide.
+                               HEAT2D5 PLAIN: sweeps fused per launch (1..16); with more than one,
+                               tile_x = tile_y = 16 or 32 is the square output tile (default 32) */
     int32_t tile_map;       /* saturated forms, order of blocks over tiles: 0 = let the plan decide,
                                1 = natural (x fastest), 2 = XCD-chunked (each of the 8 XCDs gets one
                                contiguous run of tiles, so neighbours share an L2) */

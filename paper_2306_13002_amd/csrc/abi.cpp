@@ -368,7 +368,7 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
         return fail(STENCIL_E_UNSUPPORTED, "kind %d has no saturated form", p->kind);
     const bool open = !is_point_form(dv) && (dv == STENCIL_AUTO || !d->tile_x || !d->tile_y || !d->zblock || !d->tile_map);
     if (d->tune == STENCIL_TUNE_MODEL && open) {
-        TuneRequest rq{has_sat ? dv : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map};
+        TuneRequest rq{has_sat ? dv : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map, d->bc};
         TuneEntry e{};
         stencil_status st = tune_model(p, rq, &e);
         if (st == STENCIL_OK) {
@@ -382,7 +382,7 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
         logf("%s; falling back to exhaustive tuning", stencil_last_error());
     }
     if ((d->tune == STENCIL_TUNE_EXHAUSTIVE || d->tune == STENCIL_TUNE_MODEL) && open) {
-        TuneRequest rq{has_sat ? dv : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map};
+        TuneRequest rq{has_sat ? dv : (int)STENCIL_PLAIN, d->tile_x, d->tile_y, d->zblock, d->tile_map, d->bc};
         const std::string key = tune_key(p, rq);
         TuneEntry e{};
         if (!tune_lookup(key, &e)) {
@@ -402,9 +402,13 @@ stencil_status choose_config(stencil_plan_s *p, const stencil_desc *d) {
     if (d->tile_x) t.tx = d->tile_x;
     if (d->tile_y) t.ty = d->tile_y;
     if (d->zblock) t.tz = d->zblock;
+    // HEAT2D5 PLAIN with fused sweeps: square 32 x 32 output tiles unless given
+    if (p->kind == STENCIL_HEAT2D5 && t.tz > 1 && !d->tile_x && !d->tile_y) t.tx = t.ty = 32;
     if (!ops->tile_ok(v, t))
         return fail(STENCIL_E_UNSUPPORTED, "tile (%d, %d, %d) is not offered for kind %d variant %d", t.tx, t.ty, t.tz,
                     p->kind, v);
+    if (p->kind == STENCIL_HEAT2D5 && t.tz > 1 && p->bc != STENCIL_BC_DIRICHLET)
+        return fail(STENCIL_E_UNSUPPORTED, "HEAT2D5: fused sweeps (zblock > 1) need Dirichlet boundaries");
     p->variant = v;
     p->tile = t;
     p->remap = d->tile_map ? (d->tile_map == 2) : default_remap(p->kind);
@@ -468,14 +472,20 @@ hipError_t run_sweeps(stencil_plan_s *p, void *const *fields, SweepArgs a, int i
     const bool wave = p->kind == STENCIL_WAVE25;
     const int eb = elem_bytes(p->dtype);
     void *src = wave ? fields[1] : fields[0], *dst = wave ? fields[0] : fields[1];
-    const int per = sweeps_per_launch(p->variant);
+    // sweeps per launch: the two-sweep form does two (an odd count starts with
+    // one single-sweep launch); fused HEAT2D5 sweeps do tile.tz (the first
+    // launch takes the remainder of the count)
+    const int per = launch_sweeps(p->kind, p->variant, p->tile);
+    const bool fused = p->kind == STENCIL_HEAT2D5 && per > 1;
     hipError_t e;
     *launches = 0;
     for (int t = 0; t < iterations;) {
         if (p->bc == STENCIL_BC_PERIODIC && (e = launch_periodic_fill(src, eb, p->g, p->rz, s)) != hipSuccess)
             return e;
-        const int v = (t == 0 && (iterations % per)) ? V_SATURATED : p->variant;
-        const int adv = sweeps_per_launch(v);
+        const int first = iterations % per;
+        const int v = (!fused && t == 0 && first) ? V_SATURATED : p->variant;
+        const int adv = fused ? (t == 0 && first ? first : per) : sweeps_per_launch(v);
+        a.sweeps = adv;
         a.src = src;
         a.dst = dst;
         a.part = (t + adv == iterations) ? part : nullptr;

@@ -214,7 +214,13 @@ bool load_model(std::vector<float> &model) {
 // The cost model's candidates: the exhaustive tuner's, the two-sweep form
 // included (feature 10 tells it apart, and the training campaign times it).
 std::vector<Cand> model_candidates(const KindOps *ops, int kind, const Geom &g, const TuneRequest &rq) {
-    return tune_candidates(ops, kind, g, rq);
+    // HEAT2D5's fused plain sweeps (tile.tz > 1) lie outside what the model was
+    // trained on; exhaustive tuning weighs them
+    std::vector<Cand> c = tune_candidates(ops, kind, g, rq);
+    c.erase(std::remove_if(c.begin(), c.end(),
+                           [kind](const Cand &x) { return kind == STENCIL_HEAT2D5 && x.tile.tz > 1; }),
+            c.end());
+    return c;
 }
 
 stencil_status tune_model(stencil_plan_s *p, const TuneRequest &rq, TuneEntry *best) {
@@ -252,7 +258,7 @@ stencil_status stencil_candidates(const stencil_desc *d, int32_t max, int32_t *o
     int rz = 0;
     stencil_status st = validate_desc(d, g, rz);
     if (st != STENCIL_OK) return st;
-    TuneRequest rq{d->variant, d->tile_x, d->tile_y, d->zblock, d->tile_map};
+    TuneRequest rq{d->variant, d->tile_x, d->tile_y, d->zblock, d->tile_map, d->bc};
     const std::vector<Cand> c = model_candidates(ops_for(d->kind), d->kind, g, rq);
     *n = (int32_t)c.size();
     for (int i = 0; i < (int)c.size() && i < max; ++i) {

@@ -46,6 +46,73 @@ __global__ void heat2d5_plain(const double *__restrict__ src, double *__restrict
     }
 }
 
+// PLAIN 2-D with fused sweeps: one launch performs k sweeps of the plain
+// body.  A block owns an OT x OT output tile; it loads the tile and a k-cell
+// ring around it into LDS, runs sweep s = 1..k on the cells within k - s of
+// the tile (each from the previous sweep's values, ping-ponging two LDS
+// buffers, one barrier per sweep), and writes the tile.  The ring is
+// recomputed by every block that needs it, never exchanged.  Every value is
+// computed with the plain body's operands and order, so the result equals k
+// single launches bit for bit; cells that are not interior keep their value
+// (Dirichlet), cells outside the padded array hold 0 and are read by none.
+// The residual is the last sweep's, summed per block in the block's order.
+// Block 16 x 16 threads; k <= kFuseMax.
+constexpr int kFuseMax = 16;
+
+template <int OT>
+__global__ __launch_bounds__(256) void heat2d5_fused(const double *__restrict__ src, double *__restrict__ dst, Geom g,
+                                                     double cc, double cn, int k, double *__restrict__ part) {
+    constexpr int S = OT + 2 * kFuseMax;
+    __shared__ double buf[2][S * S];
+    __shared__ double red[kMaxWaves];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int L = OT + 2 * k;                                           // region side (<= S)
+    const int X0 = blockIdx.x * OT + 1 - k, Y0 = blockIdx.y * OT + 1 - k;  // padded coords of region cell (0, 0)
+    const int PX = g.nx + 2, PY = g.ny + 2;
+    for (int cy = ty; cy < L; cy += 16)
+        for (int cx = tx; cx < L; cx += 16) {
+            const int X = X0 + cx, Y = Y0 + cy;
+            buf[0][cy * L + cx] = (X >= 0 && X < PX && Y >= 0 && Y < PY) ? src[(long long)Y * g.py + X] : 0.0;
+        }
+    __syncthreads();
+    int a = 0;
+    for (int s = 1; s <= k; ++s) {
+        const double *A = buf[a];
+        double *B = buf[a ^ 1];
+        for (int cy = s + ty; cy < L - s; cy += 16)
+            for (int cx = s + tx; cx < L - s; cx += 16) {
+                const int X = X0 + cx, Y = Y0 + cy, e = cy * L + cx;
+                const double u = A[e];
+                double v = u;
+                if (X >= 1 && X <= g.nx && Y >= 1 && Y <= g.ny) {
+                    v = cc * u;
+                    v = v + cn * A[e - 1];
+                    v = v + cn * A[e + 1];
+                    v = v + cn * A[e - L];
+                    v = v + cn * A[e + L];
+                }
+                B[e] = v;
+            }
+        __syncthreads();
+        a ^= 1;
+    }
+    const double *F = buf[a], *P = buf[a ^ 1];  // sweep k and sweep k-1 (the loaded values when k = 1)
+    double d2 = 0.0;
+    for (int cy = k + ty; cy < k + OT; cy += 16)
+        for (int cx = k + tx; cx < k + OT; cx += 16) {
+            const int X = X0 + cx, Y = Y0 + cy, e = cy * L + cx;
+            if (X <= g.nx && Y <= g.ny) {
+                dst[(long long)Y * g.py + X] = F[e];
+                const double d = F[e] - P[e];
+                d2 = d2 + d * d;
+            }
+        }
+    if (part) {
+        const double sum = block_sum_f64(d2, red);
+        if (tx == 0 && ty == 0) part[block_linear_id()] = sum;
+    }
+}
+
 // Plain 3-D body for one block-shaped tile (bx, by, bz) of blockDim points;
 // returns this thread's squared change.
 __device__ __forceinline__ double heat3d7_plain_tile(const double *__restrict__ src, double *__restrict__ dst,
@@ -375,12 +442,29 @@ bool plain_tile_ok(Tile t) {
     return t.tx >= 1 && t.ty >= 1 && t.tz >= 1 && n % 64 == 0 && n <= 1024;
 }
 
-bool h2_tile_ok(int v, Tile t) { return v == V_PLAIN && plain_tile_ok(t) && t.tz == 1; }
+// HEAT2D5 PLAIN tiles: (tx, ty, 1) threads, one point each, one sweep per
+// launch; or (OT, OT, k) with OT = 16 or 32: fused sweeps, up to k per launch
+bool h2_tile_ok(int v, Tile t) {
+    if (v != V_PLAIN) return false;
+    if (t.tz == 1) return plain_tile_ok(t);
+    return t.tx == t.ty && (t.tx == 16 || t.tx == 32) && t.tz >= 2 && t.tz <= kFuseMax;
+}
 
 long long h2_nblocks(int, Tile t, const Geom &g) { return cdiv(g.nx, t.tx) * cdiv(g.ny, t.ty); }
 
 hipError_t h2_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
     if (v != V_PLAIN) return hipErrorInvalidValue;
+    if (t.tz > 1) {
+        if (a.sweeps < 1 || a.sweeps > t.tz) return hipErrorInvalidValue;
+        dim3 grid(cdiv(a.g.nx, t.tx), cdiv(a.g.ny, t.ty), 1), block(16, 16, 1);
+        if (t.tx == 16)
+            hipLaunchKernelGGL(heat2d5_fused<16>, grid, block, 0, s, (const double *)a.src, (double *)a.dst, a.g,
+                               a.c[0], a.c[1], a.sweeps, a.part);
+        else
+            hipLaunchKernelGGL(heat2d5_fused<32>, grid, block, 0, s, (const double *)a.src, (double *)a.dst, a.g,
+                               a.c[0], a.c[1], a.sweeps, a.part);
+        return hipGetLastError();
+    }
     dim3 grid(cdiv(a.g.nx, t.tx), cdiv(a.g.ny, t.ty), 1), block(t.tx, t.ty, 1);
     hipLaunchKernelGGL(heat2d5_plain, grid, block, 0, s, (const double *)a.src, (double *)a.dst, a.g, a.c[0],
                        a.c[1], a.part);

@@ -52,6 +52,7 @@ struct SweepArgs {
     GenTab gen;               // GENERIC tap tables
     int elem_bytes;           // storage size (GENERIC: 4 or 8)
     const RtcSpec *rtc;       // GENERIC saturated: generated kernels (nullptr: table-driven kernel)
+    int sweeps = 1;           // HEAT2D5 PLAIN with fused sweeps (tile.tz > 1): sweeps this launch performs
 };
 
 // Batched runs: one problem of a batch and one work item (a tile of a

@@ -87,6 +87,13 @@ std::vector<Cand> tune_candidates(const KindOps *ops, int kind, const Geom &g, c
     if (want_v(V_PLAIN))
         for (const Tile &t : kPlainTiles)
             if (ops->tile_ok(V_PLAIN, t) && tile_fits(t)) out.push_back({V_PLAIN, t, 0});
+    // HEAT2D5 PLAIN with fused sweeps (Dirichlet): square output tiles, 2..16 sweeps per launch
+    if (want_v(V_PLAIN) && kind == STENCIL_HEAT2D5 && rq.bc == STENCIL_BC_DIRICHLET)
+        for (int ot : {16, 32})
+            for (int k : {2, 4, 5, 8, 10, 16}) {
+                const Tile t{ot, ot, k};
+                if (ops->tile_ok(V_PLAIN, t) && tile_fits(t)) out.push_back({V_PLAIN, t, 0});
+            }
     // the two-sweep Poisson kernel addresses a plane with 32-bit byte offsets
     const bool sat2_fits = kind != STENCIL_POISSON19 || g.pz * (long long)sizeof(float) <= kMaxPlaneBytes32;
     if ((rq.variant == V_SAT2 || rq.variant == STENCIL_AUTO) && ops->sat2_tiles && sat2_fits) {
@@ -147,9 +154,9 @@ struct Buffers {
 
 std::string tune_key(const stencil_plan_s *p, const TuneRequest &rq) {
     char buf[512];
-    // "/c2": candidate set 2 (AUTO includes the two-sweep form); entries of
-    // earlier sets are not reused
-    std::snprintf(buf, sizeof buf, "k%d/d%d/bc%d/n%dx%dx%d/r%d/py%lld/pz%lld/v%d/t%d,%d,%d,%d/h%08x/c2", p->kind,
+    // "/c3": candidate set 3 (AUTO includes the two-sweep form, HEAT2D5 the
+    // fused plain sweeps); entries of earlier sets are not reused
+    std::snprintf(buf, sizeof buf, "k%d/d%d/bc%d/n%dx%dx%d/r%d/py%lld/pz%lld/v%d/t%d,%d,%d,%d/h%08x/c3", p->kind,
                   p->dtype, p->bc, p->g.nx, p->g.ny, p->g.nz, p->g.r, p->g.py, p->g.pz, rq.variant, rq.tile_x,
                   rq.tile_y, rq.zblock, rq.tile_map, p->taps_hash);
     return buf;
@@ -177,6 +184,8 @@ static double time_one(const stencil_plan_s *p, const Cand &c, Buffers &b, hipSt
     SweepArgs a = p->base_args;
     a.remap = c.remap;
     a.part = nullptr;
+    const int per = launch_sweeps(p->kind, c.variant, c.tile);
+    a.sweeps = per;
     for (int i = 0; i < b.nc; ++i) a.coefs[i] = b.c[i];
     std::vector<double> ts;
     const bool wave = p->kind == STENCIL_WAVE25;
@@ -193,7 +202,7 @@ static double time_one(const stencil_plan_s *p, const Cand &c, Buffers &b, hipSt
         if ((*err = hipEventSynchronize(e1)) != hipSuccess) return 0;
         float ms = 0;
         if ((*err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return 0;
-        if (r > 0) ts.push_back(1e3 * ms / (T * sweeps_per_launch(c.variant)));
+        if (r > 0) ts.push_back(1e3 * ms / (T * per));
     }
     std::sort(ts.begin(), ts.end());
     return ts[ts.size() / 2];

@@ -16,7 +16,15 @@ namespace stn {
 // are searched; other values restrict the candidates.
 struct TuneRequest {
     int variant, tile_x, tile_y, zblock, tile_map;
+    int bc = STENCIL_BC_DIRICHLET;  // fused HEAT2D5 sweeps are offered for Dirichlet plans only
 };
+
+// Sweeps one launch of (kind, variant, tile) performs: the two-sweep form
+// does two; HEAT2D5 PLAIN with tile.tz > 1 fuses tile.tz sweeps per launch.
+inline int launch_sweeps(int kind, int variant, const Tile &t) {
+    if (kind == STENCIL_HEAT2D5 && variant == V_PLAIN && t.tz > 1) return t.tz;
+    return sweeps_per_launch(variant);
+}
 
 struct TuneEntry {
     int variant;  // V_PLAIN / V_SATURATED

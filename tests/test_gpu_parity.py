@@ -81,6 +81,35 @@ def test_heat2d5_workload_full(dev):
     assert got.min() >= 0 and got.max() <= u0.max()
 
 
+@pytest.mark.parametrize("n", [(37, 29), (256, 256), (1, 1), (65, 3), (33, 17)])
+@pytest.mark.parametrize("tile", [(16, 16, 2), (16, 16, 5), (32, 32, 3), (32, 32, 10), (32, 32, 16)])
+def test_heat2d5_fused_sweeps_bitwise(dev, n, tile):
+    # k sweeps per launch from an LDS tile with a k-cell ring: the grid equals
+    # the oracle bit for bit for sweep counts below, at and above k (the first
+    # launch takes the remainder), the residual within rounding of its order
+    u0 = synth.heat2d5_input(n[0], ny=n[1])
+    k = tile[2]
+    for T in sorted({1, max(1, k - 1), k, 2 * k + 1}):
+        want, wr = oracle.heat(u0, T, 0.6, 0.1)
+        got, gr = run_jacobi("heat2d5", u0, n, dev, T, coef=(0.6, 0.1), variant="plain", tile=tile)
+        assert np.array_equal(got, want), T
+        assert abs(gr - wr) <= 1e-10 * wr, T
+
+
+def test_heat2d5_fused_sweeps_rules(dev):
+    # zblock alone picks the 32 x 32 fused tile; periodic boundaries and
+    # tiles outside the offered set are refused before anything runs
+    from paper_2306_13002_amd.stencil import E_INVAL, E_UNSUPPORTED, StencilError
+
+    with Plan("heat2d5", (64, 64), variant="plain", coef=(0.6, 0.1), tile=(0, 0, 8)) as p:
+        assert tuple(p.config()["tile"]) == (32, 32, 8)
+    for kw in (dict(tile=(32, 32, 4), bc="periodic"), dict(tile=(64, 4, 4)), dict(tile=(32, 32, 17)),
+               dict(tile=(16, 32, 4))):
+        with pytest.raises(StencilError) as e:
+            Plan("heat2d5", (64, 64), variant="plain", coef=(0.6, 0.1), **kw)
+        assert e.value.status in (E_UNSUPPORTED, E_INVAL), kw
+
+
 # ---------------------------------------------------------------- heat3d7
 N3 = (70, 37, 29)
 

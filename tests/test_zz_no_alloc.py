@@ -80,11 +80,13 @@ CASES = [
     ("poisson19", dict(variant="saturated_t2", omega=0.8), _p19_case, (127, 40, 66), (30, 11, 17), 3),
     ("poisson19", dict(variant="plain", omega=0.8), _p19_case, (127, 40, 66), (30, 11, 17), 2),
     ("heat2d5", dict(variant="plain", coef=(0.6, 0.1)), _heat2_case, (300, 211), (37, 29), 3),
+    ("heat2d5", dict(variant="plain", coef=(0.6, 0.1), tile=(32, 32, 4)), _heat2_case, (300, 211), (37, 29), 7),
 ]
 
 
 @pytest.mark.parametrize("kind,kw,build,n_big,n_small,T", CASES,
-                         ids=[f"{c[0]}-{c[1]['variant']}" for c in CASES])
+                         ids=[f"{c[0]}-{c[1]['variant']}" + ("-fused" if c[1].get("tile", (0, 0, 1))[2] > 1 and c[0] == "heat2d5"
+                                                            else "") for c in CASES])
 def test_noalloc_matches_run_twice_second_smaller(dev, kind, kw, build, n_big, n_small, T):
     print(f"[noalloc] {kind} {kw['variant']} {n_big} then {n_small}, T={T}", flush=True)
     for n in (n_big, n_small):
