@@ -137,6 +137,9 @@ def setup_workload(name, variant, dev, torch, synth, Plan, plan_kw=None):
         meta = dict(workload=f"{name} Jacobi heat, interior {n}, FP64, {T} sweeps + residual", interior=list(n),
                     iterations=T, bytes_per_update=16, kernel_tag=f"{name}_{variant}", source="heat.hip",
                     storage="f64", sweeps_per_launch=2 if variant == "saturated_t2" else 1)
+        fuse = plan.config()["tile"][2] if name == "heat2d5" else 1
+        if fuse > 1:  # plain sweeps fused per launch (the first launch of a run takes the remainder)
+            meta.update(kernel_tag="heat2d5_fused", sweeps_per_launch=fuse)
         return plan, step, reset, pts * T, T, meta
     if name == "generic":
         w = synth.generic_box_workload()
@@ -255,33 +258,13 @@ def setup_workload(name, variant, dev, torch, synth, Plan, plan_kw=None):
 
 def time_variant(name, variant, steps, warmup, dev, torch, synth, Plan, plan_kw=None):
     plan, step, reset, pts, T, meta = setup_workload(name, variant, dev, torch, synth, Plan, plan_kw)
-    plan.profile(True)
-    for _ in range(warmup):
-        reset()
-        step()
-    torch.cuda.synchronize()
-    sweep_ms = 0.0
-    sweeps = 0
-    resid = None
     # Each timed step continues the iteration from the previous state: the
     # same work on the same grid (the restore copy is done once, untimed).
-    reset()
-    torch.cuda.synchronize()
-    per_step = []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        resid = step()
-        ms, n = plan.profile_read()
-        sweep_ms += ms
-        sweeps += n
-        per_step.append(ms / max(1, n))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    r = timed(plan, step, reset, steps, warmup, torch)
     cfg = plan.config()
     plan.close()
-    per_step.sort()
-    return dict(wall=wall, pts=pts, sweep_ms=sweep_ms, sweeps=sweeps, resid=resid, meta=meta, cfg=cfg, T=T,
-                sweep_ms_median=per_step[len(per_step) // 2], sweep_ms_best=per_step[0])
+    return dict(wall=r["wall"], pts=pts, sweep_ms=r["sweep_ms"], sweeps=r["sweeps"], resid=r["resid"], meta=meta,
+                cfg=cfg, T=T, sweep_ms_median=r["sweep_ms_median"], sweep_ms_best=r["sweep_ms_best"])
 
 
 def cpu_threads():
@@ -484,12 +467,17 @@ def bench_lhs(a, torch):
             if best is None or us < best[1]:
                 best = (t, us)
         pl = plans[(f, best[0])]
-        time_plan(pl, a.warmup)
+        # the wall clock with event profiling off, then the same steps profiled
+        pl.profile(False)
+        for _ in range(a.warmup):
+            pl.run(ins, outs, synth.LHS_PARAMS)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ms = time_plan(pl, a.steps)
+        for _ in range(a.steps):
+            pl.run(ins, outs, synth.LHS_PARAMS)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        ms = time_plan(pl, a.steps)
         launch = sum(ms) / len(ms) / 1e3
         res[f] = {"value": pts * a.steps / wall, "ms_per_step": wall * 1e3 / a.steps, "avg_launch_us": launch * 1e6,
                   "algorithmic_gbs": bytes_per_pt * pts / launch / 1e9, "tile": list(best[0]), **pl.info()}
@@ -586,25 +574,32 @@ def region(lo, hi, r):
 
 def timed(plan, step, reset, steps, warmup, torch):
     """W untimed steps, then K steps timed by the wall clock (synchronized on
-    both sides) and by the plan's HIP events around its sweep launches on
-    the stream they are launched on."""
-    plan.profile(True)
+    both sides) with the plan's event profiling off, then K more steps with
+    it on, for the per-sweep kernel times: HIP events on the stream the
+    sweeps are launched on.  (The events and their read-back add a few us per
+    step, most of a step for the smallest workloads, so they stay out of the
+    wall-clock region.)"""
+    plan.profile(False)
     for _ in range(warmup):
         reset()
         step()
     reset()
     torch.cuda.synchronize()
-    sweep_ms, sweeps, per = 0.0, 0, []
     resid = None
     t0 = time.perf_counter()
     for _ in range(steps):
         resid = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.profile(True)
+    sweep_ms, sweeps, per = 0.0, 0, []
+    for _ in range(steps):
+        step()
         ms, n = plan.profile_read()
         sweep_ms += ms
         sweeps += n
         per.append(ms / max(1, n))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    plan.profile(False)
     per.sort()
     return dict(wall=wall, sweep_ms=sweep_ms, sweeps=sweeps, resid=resid, sweep_ms_median=per[len(per) // 2],
                 sweep_ms_best=per[0])

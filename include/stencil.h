@@ -70,7 +70,9 @@ typedef enum {
  *           that needs it), with the plain body's operands and order, so the
  *           grid equals k single-sweep launches bit for bit (the residual is
  *           the same sum taken in another order).  A run of T sweeps makes
- *           ceil(T/k) launches, the first doing T mod k when that is not 0.
+ *           ceil(T/k) launches, the first doing T mod k when that is not 0;
+ *           each launch writes its destination's boundary ring, so the run
+ *           makes no separate halo copy (fields[1] ends with the same ring).
  * HEAT3D7   the same with -z, +z added; r = 1, F64.
  * POISSON19 19-point variable-coefficient pressure relaxation (the halo-3D
  *           CFD class of the paper's NPB/SPEC tables), F32 storage, FP64

@@ -56,6 +56,7 @@ __global__ void heat2d5_plain(const double *__restrict__ src, double *__restrict
 // single launches bit for bit; cells that are not interior keep their value
 // (Dirichlet), cells outside the padded array hold 0 and are read by none.
 // The residual is the last sweep's, summed per block in the block's order.
+// The launch also writes dst's boundary ring (the run needs no halo copy).
 // Block 16 x 16 threads; k <= kFuseMax.
 constexpr int kFuseMax = 16;
 
@@ -106,6 +107,18 @@ __global__ __launch_bounds__(256) void heat2d5_fused(const double *__restrict__ 
                 const double d = F[e] - P[e];
                 d2 = d2 + d * d;
             }
+        }
+    // The boundary ring of dst (Dirichlet: the loaded values, unchanged by
+    // every sweep; buf[0] holds them at every region cell), so no separate
+    // halo copy has to precede the launch: each ring cell is written by the
+    // block whose tile holds its nearest interior cell.
+    for (int cy = k - 1 + ty; cy <= k + OT; cy += 16)
+        for (int cx = k - 1 + tx; cx <= k + OT; cx += 16) {
+            const int X = X0 + cx, Y = Y0 + cy;
+            const bool ring = X >= 0 && X < PX && Y >= 0 && Y < PY && (X == 0 || X == PX - 1 || Y == 0 || Y == PY - 1);
+            const int Xi = min(max(X, 1), g.nx), Yi = min(max(Y, 1), g.ny);
+            if (ring && (Xi - 1) / OT == (int)blockIdx.x && (Yi - 1) / OT == (int)blockIdx.y)
+                dst[(long long)Y * g.py + X] = buf[0][cy * L + cx];
         }
     if (part) {
         const double sum = block_sum_f64(d2, red);

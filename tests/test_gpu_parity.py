@@ -96,6 +96,25 @@ def test_heat2d5_fused_sweeps_bitwise(dev, n, tile):
         assert abs(gr - wr) <= 1e-10 * wr, T
 
 
+@pytest.mark.parametrize("n,tile,T", [((37, 29), (16, 16, 4), 9), ((64, 33), (32, 32, 3), 6), ((1, 1), (16, 16, 2), 3)])
+def test_heat2d5_fused_sweeps_write_the_scratch_ring(dev, n, tile, T):
+    # fused runs make no halo copy: each launch writes its destination's
+    # boundary ring, so a NaN-filled scratch grid ends with the state's ring
+    # and every launch reads only finite cells
+    u0 = synth.heat2d5_input(n[0], ny=n[1])
+    p = Plan("heat2d5", n, variant="plain", coef=(0.6, 0.1), tile=tile)
+    f = [_dev(u0, dev), _nan_like(u0, dev)]
+    p.run(f, iterations=T)
+    p.close()
+    a, b = f[0].cpu().numpy(), f[1].cpu().numpy()
+    ring = np.ones(u0.shape, bool)
+    ring[1:-1, 1:-1] = False
+    assert np.array_equal(b[ring], u0[ring]) and np.array_equal(a[ring], u0[ring])
+    assert np.all(np.isfinite(b))
+    want, _ = oracle.heat(u0, T, 0.6, 0.1)
+    assert np.array_equal(a, want)
+
+
 def test_heat2d5_fused_sweeps_rules(dev):
     # zblock alone picks the 32 x 32 fused tile; periodic boundaries and
     # tiles outside the offered set are refused before anything runs

@@ -74,9 +74,11 @@ def test_heat3d7_replay(dev, variant, T):
     assert abs(gr - wr) <= 1e-10 * wr
 
 
-def test_heat2d5_replay(dev):
+@pytest.mark.parametrize("tile", [(64, 4, 1), (16, 16, 4)])
+def test_heat2d5_replay(dev, tile):
+    # one sweep per launch, and fused sweeps (10 = 2 + 4 + 4; 3 = 3)
     u0 = synth.heat2d5_input(256)
-    p = Plan("heat2d5", (256, 256), variant="plain", coef=(0.6, 0.1))
+    p = Plan("heat2d5", (256, 256), variant="plain", coef=(0.6, 0.1), tile=tile)
     f = [torch.tensor(u0, device=dev), torch.zeros(u0.shape, dtype=torch.float64, device=dev)]
     init = [torch.tensor(u0, device=dev), torch.zeros(u0.shape, dtype=torch.float64, device=dev)]
     (g, _), gr = _check_replays(p, f, init, None, 10, 3)
