@@ -13,8 +13,9 @@ light-cone crops of that run and reports the max relative error (saturated
 
 Prints one JSON line.  The headline line also carries secondary objects:
 streaming ceilings of the sweeps' access shapes, poisson19 129x129x257 (F32
-storage, Infinity-Cache resident), heat3d7 160^3 and the 64-grid heat3d7
-batch.  --workload poisson19 | heat3d7 | heat2d5 | batch | generic | stream |
+storage, Infinity-Cache resident), heat3d7 160^3, the 64-grid heat3d7
+batch, and heat2d5 256^2 (one launch per sweep and fused sweeps, with the
+oracle's one-core and all-core rates).  --workload poisson19 | heat3d7 | heat2d5 | batch | generic | stream |
 copy times one of them alone (for profiling runs); --workload lhs times the
 saturator's block-tridiagonal assembly program (162^3, 75 statements) in the
 five forms of the paper's ablation.
@@ -120,7 +121,7 @@ def setup_workload(name, variant, dev, torch, synth, Plan, plan_kw=None):
         else:
             n, T, coef = (160, 160, 160), 50, (0.4, 0.1)
             u0 = synth.heat3d7_input(*n)
-        plan = Plan(name, n, variant=variant if name == "heat3d7" else "plain", coef=coef, tune=TUNE)
+        plan = Plan(name, n, variant=variant if name == "heat3d7" else "plain", coef=coef, **pk)
         f = [torch.tensor(u0, device=dev), torch.empty(u0.shape, dtype=torch.float64, device=dev)]
         base = f[0].clone()
 
@@ -904,12 +905,34 @@ def secondary_batch(a, dev, torch, synth, Plan):
             "batched_over_separate": rows["plain"]["us_per_iteration"] / rows["saturated_t2"]["us_per_iteration"]}
 
 
+def secondary_heat2d5(a, dev, torch, synth, Plan):
+    """heat2d5 256^2, 10 sweeps + residual per step (the plain form only): one
+    launch per sweep and sweeps fused per launch (tuned), and the oracle on
+    one core and on every core at once (each thread its own grid)."""
+    steps = max(50, 5 * a.steps)
+    rows, meta = {}, None
+    for label, kw in (("one_launch_per_sweep", dict(tile=(64, 8, 1))), ("fused_tuned", {})):
+        r = time_variant("heat2d5", "plain", steps, 5, dev, torch, synth, Plan, plan_kw=kw)
+        meta = r["meta"]
+        rows[label] = {"updates_per_s": r["pts"] * steps / r["wall"], "us_per_step": r["wall"] * 1e6 / steps,
+                       "tile": list(r["cfg"]["tile"])}
+    out = {"workload": meta["workload"], "forms": rows,
+           "fused_over_one_launch_per_sweep": rows["fused_tuned"]["updates_per_s"] /
+           rows["one_launch_per_sweep"]["updates_per_s"]}
+    if not a.no_cpu:
+        cb = cpu_baseline("heat2d5")
+        out["cpu_baseline"] = cb
+        out["gpu_over_cpu_all_cores"] = rows["fused_tuned"]["updates_per_s"] / cb["all_cores"]["value"]
+    return out
+
+
 def run_secondary(out, a, dev, torch, synth, Plan):
     sec = {}
     for key, fn in (("stream", lambda: stream_ceilings(torch, dev)),
                     ("poisson19", lambda: secondary_jacobi("poisson19", a, dev, torch, synth, Plan)),
                     ("heat3d7", lambda: secondary_jacobi("heat3d7", a, dev, torch, synth, Plan)),
-                    ("batch", lambda: secondary_batch(a, dev, torch, synth, Plan))):
+                    ("batch", lambda: secondary_batch(a, dev, torch, synth, Plan)),
+                    ("heat2d5", lambda: secondary_heat2d5(a, dev, torch, synth, Plan))):
         try:
             sec[key] = fn()
         except Exception as e:  # a secondary failure must not hide the headline
