@@ -248,8 +248,8 @@ stencil_status stencil_run_noalloc(stencil_plan_t p, void *const *fields, const 
  * (new - old)^2 (POISSON19: sum of ss^2).  Paper: not defined there (it
  * rewrites loop bodies and reports kernel times); this is the FP64 sum of
  * squared updates a Jacobi-type solver checks for convergence.  Reduces the per-block partials in
- * a fixed order (bitwise reproducible), copies 8 bytes to the host and
- * synchronizes `stream`.  E_STATE if no sweep has run on this plan. */
+ * a fixed order (bitwise reproducible) into a pinned host word of the plan
+ * and synchronizes `stream`.  E_STATE if no sweep has run on this plan. */
 stencil_status stencil_residual(stencil_plan_t p, double *host_out, void *stream);
 
 /* Per-problem residuals of the last run of a batch plan (count = number of

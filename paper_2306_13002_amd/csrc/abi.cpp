@@ -297,9 +297,9 @@ stencil_status alloc_plan_buffers(stencil_plan_s *p) {
         return fail(STENCIL_E_NOMEM, "hipMalloc residual partials (%lld blocks): %s", p->nblocks, hipGetErrorString(e));
     if ((e = hipMalloc(&p->d_red, sizeof(double) * kReduceBlocks)) != hipSuccess)
         return fail(STENCIL_E_NOMEM, "hipMalloc reduction scratch: %s", hipGetErrorString(e));
-    if ((e = hipMalloc(&p->d_result, sizeof(double))) != hipSuccess)
-        return fail(STENCIL_E_NOMEM, "hipMalloc result: %s", hipGetErrorString(e));
-    if ((e = hipHostMalloc(&p->h_result, sizeof(double), hipHostMallocDefault)) != hipSuccess)
+    // the reduction writes the residual straight into this pinned, coherent
+    // host word (no device-to-host copy per residual)
+    if ((e = hipHostMalloc(&p->h_result, sizeof(double), hipHostMallocCoherent)) != hipSuccess)
         return fail(STENCIL_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
     if ((e = hipEventCreate(&p->ev0)) != hipSuccess || (e = hipEventCreate(&p->ev1)) != hipSuccess)
         return hip_fail(e, "hipEventCreate");
@@ -326,7 +326,6 @@ void free_plan(stencil_plan_s *p) {
         delete p->rg;
     }
     delete p->rtc;
-    if (p->d_result) (void)hipFree(p->d_result);
     if (p->h_result) (void)hipHostFree(p->h_result);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
@@ -698,10 +697,8 @@ stencil_status stencil_residual(stencil_plan_t p, double *host_out, void *stream
     hipStream_t s = (hipStream_t)stream_;
     if (p->batch) return batch_residuals(p, host_out, 1, s);
     hipError_t e;
-    if ((e = launch_reduce_partials(p->d_part, p->nblocks, p->d_red, p->d_result, s)) != hipSuccess)
+    if ((e = launch_reduce_partials(p->d_part, p->nblocks, p->d_red, p->h_result, s)) != hipSuccess)
         return hip_fail(e, "reduce launch");
-    if ((e = hipMemcpyAsync(p->h_result, p->d_result, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
-        return hip_fail(e, "hipMemcpyAsync");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     *host_out = *p->h_result;
     return STENCIL_OK;

@@ -64,8 +64,7 @@ struct stencil_plan_s {
     double *d_part = nullptr;   // device: per-block residual partials of the last sweep
     double *d_red = nullptr;    // device: first-pass sums of the residual reduction
     int remap = 1;              // XCD-chunked tile order for the saturated forms
-    double *d_result = nullptr; // device: reduced residual
-    double *h_result = nullptr; // pinned host copy
+    double *h_result = nullptr; // pinned coherent host word: the reduced residual
     bool has_resid = false;
     bool profiling = false, prof_valid = false;
     int prof_sweeps = 0;

@@ -172,6 +172,13 @@ hipError_t launch_reduce_partials(const double *part, long long n, double *scrat
     long long chunk = cdiv(n, kReduceBlocks);
     if (chunk < 1024) chunk = 1024;
     const long long nb = cdiv(n, chunk);
+    if (nb == 1) {
+        // One chunk: a second pass would add zeros to this sum and return it
+        // unchanged (residuals are sums of squares, never -0), so the single
+        // block writes the total itself and one launch is saved.
+        hipLaunchKernelGGL(reduce_pass1_kernel, dim3(1), dim3(256), 0, s, part, n, chunk, out);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(reduce_pass1_kernel, dim3((unsigned)nb), dim3(256), 0, s, part, n, chunk, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
