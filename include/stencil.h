@@ -168,7 +168,8 @@ typedef struct {
     int32_t tile_y;         /* rows per block tile; 0 = let the plan decide */
     int32_t zblock;         /* z planes per block (saturated forms); 0 = let the plan decide.
                                HEAT2D5 PLAIN: sweeps fused per launch (1..16); with more than one,
-                               tile_x = tile_y = 16 or 32 is the square output tile (default 32) */
+                               tile_x = tile_y is the square output tile: 16 or 32 (default 32), or
+                               any size with tile_x + 2 * zblock <= 32 (one region cell per thread) */
     int32_t tile_map;       /* saturated forms, order of blocks over tiles: 0 = let the plan decide,
                                1 = natural (x fastest), 2 = XCD-chunked (each of the 8 XCDs gets one
                                contiguous run of tiles, so neighbours share an L2) */

@@ -126,6 +126,68 @@ __global__ __launch_bounds__(256) void heat2d5_fused(const double *__restrict__ 
     }
 }
 
+// The same fused sweeps with one region cell per thread, for regions of at
+// most 32 x 32 cells (OT + 2k <= 32): a 1-D block of L*L threads rounded up
+// to whole waves, thread c holding region cell (c mod L, c div L).  Each
+// thread keeps its own cell's value in a register from sweep to sweep and
+// reads only its four neighbours from the previous sweep's LDS buffer, so a
+// sweep is four independent LDS reads, the update, one LDS write and one
+// barrier, with every lane of the block's waves at work.  Operands and order
+// are the plain body's, as above; the padding threads past L*L take part in
+// the barriers and the residual sum only.
+__global__ __launch_bounds__(1024) void heat2d5_fused_cell(const double *__restrict__ src, double *__restrict__ dst,
+                                                           Geom g, double cc, double cn, int OT, int k,
+                                                           double *__restrict__ part) {
+    __shared__ double buf[2][32 * 32];
+    __shared__ double red[kMaxWaves];
+    const int L = OT + 2 * k, c = threadIdx.x;
+    const bool cell = c < L * L;
+    const int cx = c % L, cy = c / L;
+    const int X = blockIdx.x * OT + 1 - k + cx, Y = blockIdx.y * OT + 1 - k + cy;  // padded coords
+    const int PX = g.nx + 2, PY = g.ny + 2;
+    const bool inarr = cell && X >= 0 && X < PX && Y >= 0 && Y < PY;
+    const bool interior = X >= 1 && X <= g.nx && Y >= 1 && Y <= g.ny;
+    const long long q = (long long)Y * g.py + X;
+    const double u0 = inarr ? src[q] : 0.0;
+    double u = u0, prev = u0;  // this cell after the last sweep and the one before
+    if (cell) buf[0][c] = u0;
+    __syncthreads();
+    for (int s = 1; s <= k; ++s) {
+        const double *A = buf[(s - 1) & 1];
+        if (cell && cx >= s && cx < L - s && cy >= s && cy < L - s) {  // within k - s of the tile
+            double v = u;
+            if (interior) {
+                v = cc * u;
+                v = v + cn * A[c - 1];
+                v = v + cn * A[c + 1];
+                v = v + cn * A[c - L];
+                v = v + cn * A[c + L];
+            }
+            prev = u;
+            u = v;
+            buf[s & 1][c] = v;
+        }
+        __syncthreads();
+    }
+    double d2 = 0.0;
+    if (cell && cx >= k && cx < k + OT && cy >= k && cy < k + OT && X <= g.nx && Y <= g.ny) {
+        dst[q] = u;
+        const double d = u - prev;
+        d2 = d * d;
+    }
+    // dst's boundary ring, as in heat2d5_fused: the loaded values, each cell
+    // written by the block whose tile holds its nearest interior cell
+    if (inarr && cx >= k - 1 && cx <= k + OT && cy >= k - 1 && cy <= k + OT &&
+        (X == 0 || X == PX - 1 || Y == 0 || Y == PY - 1)) {
+        const int Xi = min(max(X, 1), g.nx), Yi = min(max(Y, 1), g.ny);
+        if ((Xi - 1) / OT == (int)blockIdx.x && (Yi - 1) / OT == (int)blockIdx.y) dst[q] = u0;
+    }
+    if (part) {
+        const double sum = block_sum_f64(d2, red);
+        if (c == 0) part[block_linear_id()] = sum;
+    }
+}
+
 // Plain 3-D body for one block-shaped tile (bx, by, bz) of blockDim points;
 // returns this thread's squared change.
 __device__ __forceinline__ double heat3d7_plain_tile(const double *__restrict__ src, double *__restrict__ dst,
@@ -456,11 +518,16 @@ bool plain_tile_ok(Tile t) {
 }
 
 // HEAT2D5 PLAIN tiles: (tx, ty, 1) threads, one point each, one sweep per
-// launch; or (OT, OT, k) with OT = 16 or 32: fused sweeps, up to k per launch
+// launch; or (OT, OT, k): fused sweeps, up to k per launch, with one region
+// cell per thread when OT + 2k <= 32, else from a 16 x 16-thread LDS tile
+// (OT = 16 or 32)
+bool h2_cell_tile(Tile t) { return t.tx + 2 * t.tz <= 32; }
+
 bool h2_tile_ok(int v, Tile t) {
     if (v != V_PLAIN) return false;
     if (t.tz == 1) return plain_tile_ok(t);
-    return t.tx == t.ty && (t.tx == 16 || t.tx == 32) && t.tz >= 2 && t.tz <= kFuseMax;
+    return t.tx == t.ty && t.tx >= 1 && t.tz >= 2 && t.tz <= kFuseMax &&
+           (h2_cell_tile(t) || t.tx == 16 || t.tx == 32);
 }
 
 long long h2_nblocks(int, Tile t, const Geom &g) { return cdiv(g.nx, t.tx) * cdiv(g.ny, t.ty); }
@@ -470,7 +537,11 @@ hipError_t h2_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
     if (t.tz > 1) {
         if (a.sweeps < 1 || a.sweeps > t.tz) return hipErrorInvalidValue;
         dim3 grid(cdiv(a.g.nx, t.tx), cdiv(a.g.ny, t.ty), 1), block(16, 16, 1);
-        if (t.tx == 16)
+        if (h2_cell_tile(t)) {
+            const int L = t.tx + 2 * a.sweeps;  // <= 32
+            hipLaunchKernelGGL(heat2d5_fused_cell, grid, dim3((L * L + 63) / 64 * 64), 0, s, (const double *)a.src,
+                               (double *)a.dst, a.g, a.c[0], a.c[1], t.tx, a.sweeps, a.part);
+        } else if (t.tx == 16)
             hipLaunchKernelGGL(heat2d5_fused<16>, grid, block, 0, s, (const double *)a.src, (double *)a.dst, a.g,
                                a.c[0], a.c[1], a.sweeps, a.part);
         else

@@ -87,13 +87,16 @@ std::vector<Cand> tune_candidates(const KindOps *ops, int kind, const Geom &g, c
     if (want_v(V_PLAIN))
         for (const Tile &t : kPlainTiles)
             if (ops->tile_ok(V_PLAIN, t) && tile_fits(t)) out.push_back({V_PLAIN, t, 0});
-    // HEAT2D5 PLAIN with fused sweeps (Dirichlet): square output tiles, 2..16 sweeps per launch
-    if (want_v(V_PLAIN) && kind == STENCIL_HEAT2D5 && rq.bc == STENCIL_BC_DIRICHLET)
+    // HEAT2D5 PLAIN with fused sweeps (Dirichlet): square output tiles, 2..16
+    // sweeps per launch; the last six fill a 32 x 32 region exactly
+    if (want_v(V_PLAIN) && kind == STENCIL_HEAT2D5 && rq.bc == STENCIL_BC_DIRICHLET) {
+        std::vector<Tile> ft;
         for (int ot : {16, 32})
-            for (int k : {2, 4, 5, 8, 10, 16}) {
-                const Tile t{ot, ot, k};
-                if (ops->tile_ok(V_PLAIN, t) && tile_fits(t)) out.push_back({V_PLAIN, t, 0});
-            }
+            for (int k : {2, 4, 5, 8, 10, 16}) ft.push_back(Tile{ot, ot, k});
+        for (int k : {2, 4, 5, 6, 10, 12}) ft.push_back(Tile{32 - 2 * k, 32 - 2 * k, k});
+        for (const Tile &t : ft)
+            if (ops->tile_ok(V_PLAIN, t) && tile_fits(t)) out.push_back({V_PLAIN, t, 0});
+    }
     // the two-sweep Poisson kernel addresses a plane with 32-bit byte offsets
     const bool sat2_fits = kind != STENCIL_POISSON19 || g.pz * (long long)sizeof(float) <= kMaxPlaneBytes32;
     if ((rq.variant == V_SAT2 || rq.variant == STENCIL_AUTO) && ops->sat2_tiles && sat2_fits) {
@@ -154,9 +157,10 @@ struct Buffers {
 
 std::string tune_key(const stencil_plan_s *p, const TuneRequest &rq) {
     char buf[512];
-    // "/c3": candidate set 3 (AUTO includes the two-sweep form, HEAT2D5 the
-    // fused plain sweeps); entries of earlier sets are not reused
-    std::snprintf(buf, sizeof buf, "k%d/d%d/bc%d/n%dx%dx%d/r%d/py%lld/pz%lld/v%d/t%d,%d,%d,%d/h%08x/c3", p->kind,
+    // "/c4": candidate set 4 (AUTO includes the two-sweep form, HEAT2D5 the
+    // fused plain sweeps with one-cell-per-thread tiles); entries of earlier
+    // sets are not reused
+    std::snprintf(buf, sizeof buf, "k%d/d%d/bc%d/n%dx%dx%d/r%d/py%lld/pz%lld/v%d/t%d,%d,%d,%d/h%08x/c4", p->kind,
                   p->dtype, p->bc, p->g.nx, p->g.ny, p->g.nz, p->g.r, p->g.py, p->g.pz, rq.variant, rq.tile_x,
                   rq.tile_y, rq.zblock, rq.tile_map, p->taps_hash);
     return buf;

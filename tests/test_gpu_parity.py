@@ -82,10 +82,12 @@ def test_heat2d5_workload_full(dev):
 
 
 @pytest.mark.parametrize("n", [(37, 29), (256, 256), (1, 1), (65, 3), (33, 17)])
-@pytest.mark.parametrize("tile", [(16, 16, 2), (16, 16, 5), (32, 32, 3), (32, 32, 10), (32, 32, 16)])
+@pytest.mark.parametrize("tile", [(16, 16, 2), (16, 16, 5), (16, 16, 8), (12, 12, 10), (22, 22, 5), (28, 28, 2),
+                                  (3, 3, 4), (32, 32, 3), (32, 32, 10), (32, 32, 16), (16, 16, 9)])
 def test_heat2d5_fused_sweeps_bitwise(dev, n, tile):
-    # k sweeps per launch from an LDS tile with a k-cell ring: the grid equals
-    # the oracle bit for bit for sweep counts below, at and above k (the first
+    # k sweeps per launch over a k-cell ring (one region cell per thread when
+    # OT + 2k <= 32, else from a 16 x 16-thread LDS tile): the grid equals the
+    # oracle bit for bit for sweep counts below, at and above k (the first
     # launch takes the remainder), the residual within rounding of its order
     u0 = synth.heat2d5_input(n[0], ny=n[1])
     k = tile[2]
@@ -96,7 +98,8 @@ def test_heat2d5_fused_sweeps_bitwise(dev, n, tile):
         assert abs(gr - wr) <= 1e-10 * wr, T
 
 
-@pytest.mark.parametrize("n,tile,T", [((37, 29), (16, 16, 4), 9), ((64, 33), (32, 32, 3), 6), ((1, 1), (16, 16, 2), 3)])
+@pytest.mark.parametrize("n,tile,T", [((37, 29), (16, 16, 4), 9), ((64, 33), (32, 32, 3), 6), ((1, 1), (16, 16, 2), 3),
+                                      ((37, 29), (12, 12, 10), 23), ((1, 1), (28, 28, 2), 3), ((64, 33), (16, 16, 12), 13)])
 def test_heat2d5_fused_sweeps_write_the_scratch_ring(dev, n, tile, T):
     # fused runs make no halo copy: each launch writes its destination's
     # boundary ring, so a NaN-filled scratch grid ends with the state's ring
@@ -118,12 +121,16 @@ def test_heat2d5_fused_sweeps_write_the_scratch_ring(dev, n, tile, T):
 def test_heat2d5_fused_sweeps_rules(dev):
     # zblock alone picks the 32 x 32 fused tile; periodic boundaries and
     # tiles outside the offered set are refused before anything runs
+    # (20 + 2*7 > 32 and 20 is not an LDS-tile size; 12 x 12 x 1 is not a
+    # one-sweep thread block of whole waves)
     from paper_2306_13002_amd.stencil import E_INVAL, E_UNSUPPORTED, StencilError
 
     with Plan("heat2d5", (64, 64), variant="plain", coef=(0.6, 0.1), tile=(0, 0, 8)) as p:
         assert tuple(p.config()["tile"]) == (32, 32, 8)
+    with Plan("heat2d5", (64, 64), variant="plain", coef=(0.6, 0.1), tile=(22, 22, 5)) as p:
+        assert tuple(p.config()["tile"]) == (22, 22, 5)
     for kw in (dict(tile=(32, 32, 4), bc="periodic"), dict(tile=(64, 4, 4)), dict(tile=(32, 32, 17)),
-               dict(tile=(16, 32, 4))):
+               dict(tile=(16, 32, 4)), dict(tile=(20, 20, 7)), dict(tile=(12, 12, 1))):
         with pytest.raises(StencilError) as e:
             Plan("heat2d5", (64, 64), variant="plain", coef=(0.6, 0.1), **kw)
         assert e.value.status in (E_UNSUPPORTED, E_INVAL), kw
