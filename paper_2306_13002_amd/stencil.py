@@ -177,6 +177,9 @@ class _GridLayout:
         self.dtype = kw.get("dtype") or DEFAULT_DTYPE[kind]
         self.radius = int(kw.get("radius") if kw.get("radius") is not None else RADIUS.get(kind, 1))
         self.pitch = tuple(kw.get("pitch", (0, 0)))
+        # fixed per layout; the tensor checks of every run compare against them
+        self._span_n = self._span()
+        self._shape_n = self.padded_shape()
 
     def padded_shape(self):
         r = self.radius
@@ -199,16 +202,16 @@ class _GridLayout:
         want = torch.float32 if dtype_name == "f32" else torch.float64
         if not isinstance(t, torch.Tensor):
             raise TypeError(f"{what} must be a torch tensor")
-        if t.device.type != "cuda":
+        if not t.is_cuda:
             raise ValueError(f"{what} must be a device (cuda) tensor")
         if t.dtype != want:
             raise TypeError(f"{what} must be {want}, got {t.dtype}")
         if not t.is_contiguous():
             raise ValueError(f"{what} must be contiguous (use pitch= for padded rows)")
-        if t.numel() < self._span():
-            raise ValueError(f"{what} holds {t.numel()} elements, the padded grid spans {self._span()}")
-        if self.pitch == (0, 0) and tuple(t.shape) != self.padded_shape() and t.dim() != 1:
-            raise ValueError(f"{what} shape {tuple(t.shape)} != padded shape {self.padded_shape()}")
+        if t.numel() < self._span_n:
+            raise ValueError(f"{what} holds {t.numel()} elements, the padded grid spans {self._span_n}")
+        if self.pitch == (0, 0) and t.shape != self._shape_n and t.dim() != 1:
+            raise ValueError(f"{what} shape {tuple(t.shape)} != padded shape {self._shape_n}")
         return ctypes.c_void_p(t.data_ptr())
 
     def _pointers(self, fields, coef_arrays):
@@ -334,7 +337,8 @@ class BatchPlan:
         self._h = h
         self._plans = [Plan.__new__(Plan) for _ in self.n]
         for p, n in zip(self._plans, self.n):  # layout checkers only (no library handle)
-            p.kind, p.n, p.dtype, p.radius, p.pitch, p._h = "heat3d7", n, "f64", 1, (0, 0), None
+            _GridLayout.__init__(p, "heat3d7", n, dtype="f64", radius=1)
+            p._h = None
 
     def run(self, fields, iterations: int = 1, stream=None):
         """fields: one (state, scratch) pair of padded tensors per problem."""
