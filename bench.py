@@ -137,7 +137,7 @@ def setup_workload(name, variant, dev, torch, synth, Plan, plan_kw=None):
             pts *= v
         meta = dict(workload=f"{name} Jacobi heat, interior {n}, FP64, {T} sweeps + residual", interior=list(n),
                     iterations=T, bytes_per_update=16, kernel_tag=f"{name}_{variant}", source="heat.hip",
-                    storage="f64", sweeps_per_launch=2 if variant == "saturated_t2" else 1)
+                    storage="f64", sweeps_per_launch={"saturated_t2": 2, "saturated_t3": 3}.get(variant, 1))
         fuse = plan.config()["tile"][2] if name == "heat2d5" else 1
         if fuse > 1:  # plain sweeps fused per launch (the first launch of a run takes the remainder)
             meta.update(kernel_tag="heat2d5_fused", sweeps_per_launch=fuse)
@@ -181,7 +181,7 @@ def setup_workload(name, variant, dev, torch, synth, Plan, plan_kw=None):
         us = [synth.heat3d7_input(*n, stream=1 + b) for b, n in enumerate(sizes)]
         fs = [(torch.tensor(u, device=dev), torch.empty(u.shape, dtype=torch.float64, device=dev)) for u in us]
         pts = sum(n[0] * n[1] * n[2] for n in sizes)
-        if variant in ("saturated", "saturated_t2"):  # the batched graph, classes tuned
+        if variant in ("saturated", "saturated_t2", "saturated_t3"):  # the batched graph, classes tuned
             plan = BatchPlan(sizes, tune=TUNE, variant=variant)
 
             def step():
@@ -220,7 +220,8 @@ def setup_workload(name, variant, dev, torch, synth, Plan, plan_kw=None):
         meta = dict(workload="64 independent heat3d7 FP64 grids, edges 32..160 (seeded), 50 sweeps each + "
                              "residuals; batched graph vs 64 separate plain runs",
                     interior=[len(sizes), pts], iterations=T, bytes_per_update=16, kernel_tag="heat3d7_batch",
-                    source="heat.hip", storage="f64", sweeps_per_launch=2 if variant == "saturated_t2" else 1)
+                    source="heat.hip", storage="f64",
+                    sweeps_per_launch={"saturated_t2": 2, "saturated_t3": 3}.get(variant, 1))
         return plan, step, (lambda: None), pts * T, T, meta
     if name == "copy":
         # plain device-to-device copy of 1 GiB: the streaming ceiling, and the
@@ -847,7 +848,7 @@ def stream_ceilings(torch, dev, reps=10, edge=520):
 def secondary_jacobi(name, a, dev, torch, synth, Plan):
     """poisson19 129x129x257 or heat3d7 160^3: every form, tuned; per-pass and
     per-sweep-equivalent fractions kept apart; cache residency flagged."""
-    forms = ["plain", "saturated", "saturated_t2"]
+    forms = ["plain", "saturated", "saturated_t2"] + (["saturated_t3"] if name == "heat3d7" else [])
     steps = max(5, a.steps // 2)
     rows = {}
     meta = None
@@ -872,7 +873,7 @@ def secondary_jacobi(name, a, dev, torch, synth, Plan):
     for e in (meta.get("grid_total") or [x + 2 for x in meta["interior"]]):
         pts_total *= e
     ws *= pts_total
-    return {
+    out = {
         "workload": meta["workload"], "storage": meta["storage"], "working_set_bytes": ws,
         "cache_resident": ws <= INFINITY_CACHE_BYTES,
         "note": ("working set fits the 256 MB Infinity Cache: rates above are cache-assisted, not an HBM roofline"
@@ -883,12 +884,16 @@ def secondary_jacobi(name, a, dev, torch, synth, Plan):
         "temporal_blocking_gain_t2_over_saturated":
             rows["saturated"]["us_per_sweep"] / rows["saturated_t2"]["us_per_sweep"],
     }
+    if "saturated_t3" in rows:  # three sweeps per pass (heat3d7)
+        out["temporal_blocking_gain_t3_over_saturated"] = (rows["saturated"]["us_per_sweep"] /
+                                                           rows["saturated_t3"]["us_per_sweep"])
+    return out
 
 
 def secondary_batch(a, dev, torch, synth, Plan):
     steps = max(3, a.steps // 4)
     rows = {}
-    for v in ("saturated_t2", "plain"):
+    for v in ("saturated_t2", "saturated_t3", "plain"):
         r = time_variant("batch", v, steps, 1, dev, torch, synth, Plan)
         rows[v] = {"us_per_iteration": r["sweep_ms"] * 1e3 / max(1, r["sweeps"]),
                    "updates_per_s": r["pts"] * steps / r["wall"], "ms_per_step": r["wall"] * 1e3 / steps}
@@ -901,8 +906,11 @@ def secondary_batch(a, dev, torch, synth, Plan):
         v["frac_per_sweep"] = alg / (v["us_per_iteration"] * 1e-6) / 1e9 / HBM_PEAK_GBS
     return {"workload": "64 independent heat3d7 FP64 grids, edges 32..160 (seeded), 50 sweeps each + residuals",
             "updates_per_iteration": pts, "working_set_bytes": 16 * pts,
-            "forms": {"batched_graph_two_sweep": rows["saturated_t2"], "separate_plain_runs": rows["plain"]},
-            "batched_over_separate": rows["plain"]["us_per_iteration"] / rows["saturated_t2"]["us_per_iteration"]}
+            "forms": {"batched_graph_two_sweep": rows["saturated_t2"], "batched_graph_three_sweep": rows["saturated_t3"],
+                      "separate_plain_runs": rows["plain"]},
+            "batched_over_separate": rows["plain"]["us_per_iteration"] /
+                                     min(rows["saturated_t2"]["us_per_iteration"],
+                                         rows["saturated_t3"]["us_per_iteration"])}
 
 
 def secondary_heat2d5(a, dev, torch, synth, Plan):
@@ -953,7 +961,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="wave25",
                     choices=["wave25", "poisson19", "heat2d5", "heat3d7", "batch", "copy", "lhs", "generic", "stream"])
-    ap.add_argument("--variant", default="best", choices=["best", "saturated", "saturated_t2", "plain"],
+    ap.add_argument("--variant", default="best", choices=["best", "saturated", "saturated_t2", "saturated_t3", "plain"],
                     help="non-headline workloads: best = every saturated form the workload offers, tuned, the "
                          "fastest reported")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain form beside it")
@@ -1002,6 +1010,8 @@ def bench_workload(a, dev, torch, synth, Plan):
     forms = [a.variant]
     if a.variant == "best":
         forms = ["saturated", "saturated_t2"] if a.workload in ("poisson19", "heat3d7", "batch") else ["saturated"]
+        if a.workload in ("heat3d7", "batch"):  # three sweeps per pass: heat3d7 only
+            forms.append("saturated_t3")
         if a.workload == "heat2d5":  # the 2-D heat sweep has the plain form only
             forms = ["plain"]
     sat = {v: time_variant(a.workload, v, a.steps, a.warmup, dev, torch, synth, Plan) for v in forms}

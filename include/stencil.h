@@ -127,7 +127,17 @@ typedef enum { STENCIL_F32 = 1, STENCIL_F64 = 2 } stencil_dtype; /* storage type
  * Bit-identical to SATURATED at the same tile, z-block and tile map (an odd
  * sweep count starts with one SATURATED sweep).  EXHAUSTIVE and MODEL tuning
  * of AUTO consider it beside PLAIN and SATURATED (the model's form feature
- * tells the three apart; its target is the time per sweep in every form). */
+ * tells the three apart; its target is the time per sweep in every form).
+ *
+ * SATURATED_T3 (HEAT3D7, Dirichlet; single and batched plans): three sweeps
+ * per pass, one thread per column of a region two cells wider on every side
+ * than the output tile (tile_x, tile_y = 28 x 28, 28 x 20, 28 x 12 or 60 x 12);
+ * the first and second sweeps are recomputed on the ring, and every input
+ * stream is read once per three sweeps.  Bit-identical to SATURATED (a sweep
+ * count that is not a multiple of three starts with one launch of the
+ * remainder's sweeps in the same form).  EXHAUSTIVE tuning of AUTO weighs
+ * it; MODEL tuning leaves it out (outside the model's training set) and,
+ * asked for it with the shape open, tunes exhaustively. */
 typedef enum {
     STENCIL_PLAIN = 0,
     STENCIL_SATURATED = 1,
@@ -135,7 +145,8 @@ typedef enum {
     STENCIL_CSE_SAT = 3,
     STENCIL_CSE_BULK = 4,
     STENCIL_ACCSAT_POINT = 5,
-    STENCIL_SATURATED_T2 = 6
+    STENCIL_SATURATED_T2 = 6,
+    STENCIL_SATURATED_T3 = 7
 } stencil_variant;
 /* How a plan picks variant and tile when variant == AUTO or a tile field is 0:
  * FIXED uses library defaults; EXHAUSTIVE times every candidate on the device

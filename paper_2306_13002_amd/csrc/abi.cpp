@@ -87,6 +87,7 @@ int elem_bytes(int dtype) { return dtype == STENCIL_F32 ? 4 : 8; }
 Tile default_tile(int kind, int variant, const Geom &g) {
     if (variant == V_PLAIN) return kind == STENCIL_HEAT2D5 ? Tile{64, 4, 1} : Tile{128, 8, 1};
     if (variant == V_SAT2 && kind == STENCIL_POISSON19) return Tile{64, 8, g.nz < 32 ? g.nz : 32};
+    if (variant == V_SAT3) return Tile{28, 28, g.nz < 32 ? g.nz : 32};
     switch (kind) {
     case STENCIL_HEAT3D7: return Tile{32, 8, g.nz < 8 ? g.nz : 8};
     case STENCIL_POISSON19: return Tile{128, 4, g.nz < 32 ? g.nz : 32};
@@ -194,13 +195,15 @@ stencil_status validate_desc(const stencil_desc *d, Geom &g, int &rz) {
     const int k = d->kind;
     if (k < STENCIL_HEAT2D5 || k > STENCIL_GENERIC) return fail(STENCIL_E_INVAL, "unknown kind %d", k);
     if (d->dtype != STENCIL_F32 && d->dtype != STENCIL_F64) return fail(STENCIL_E_INVAL, "unknown dtype %d", d->dtype);
-    if (d->variant < STENCIL_PLAIN || d->variant > STENCIL_SATURATED_T2)
+    if (d->variant < STENCIL_PLAIN || d->variant > STENCIL_SATURATED_T3)
         return fail(STENCIL_E_INVAL, "unknown variant %d", d->variant);
     if (is_point_form(d->variant) && k != STENCIL_WAVE25 && k != STENCIL_POISSON19)
         return fail(STENCIL_E_UNSUPPORTED, "the per-point ablation forms are offered for WAVE25 and POISSON19");
     if (d->variant == STENCIL_SATURATED_T2 &&
         ((k != STENCIL_POISSON19 && k != STENCIL_HEAT3D7) || d->bc != STENCIL_BC_DIRICHLET))
         return fail(STENCIL_E_UNSUPPORTED, "the two-sweep saturated form is offered for POISSON19 and HEAT3D7 (Dirichlet)");
+    if (d->variant == STENCIL_SATURATED_T3 && (k != STENCIL_HEAT3D7 || d->bc != STENCIL_BC_DIRICHLET))
+        return fail(STENCIL_E_UNSUPPORTED, "the three-sweep saturated form is offered for HEAT3D7 (Dirichlet)");
     if (d->tune < STENCIL_TUNE_FIXED || d->tune > STENCIL_TUNE_MODEL)
         return fail(STENCIL_E_INVAL, "unknown tune mode %d", d->tune);
     if (d->bc != STENCIL_BC_DIRICHLET && d->bc != STENCIL_BC_PERIODIC)
@@ -474,10 +477,11 @@ hipError_t run_sweeps(stencil_plan_s *p, void *const *fields, SweepArgs a, int i
     const int eb = elem_bytes(p->dtype);
     void *src = wave ? fields[1] : fields[0], *dst = wave ? fields[0] : fields[1];
     // sweeps per launch: the two-sweep form does two (an odd count starts with
-    // one single-sweep launch); fused HEAT2D5 sweeps do tile.tz (the first
-    // launch takes the remainder of the count)
+    // one single-sweep launch); fused HEAT2D5 sweeps do tile.tz and the
+    // three-sweep form three (the first launch takes the remainder of the
+    // count)
     const int per = launch_sweeps(p->kind, p->variant, p->tile);
-    const bool fused = p->kind == STENCIL_HEAT2D5 && per > 1;
+    const bool fused = (p->kind == STENCIL_HEAT2D5 && per > 1) || p->variant == V_SAT3;
     hipError_t e;
     *launches = 0;
     for (int t = 0; t < iterations;) {

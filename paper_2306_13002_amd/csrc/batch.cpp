@@ -167,7 +167,8 @@ stencil_status tune_class(const std::vector<int> &members, const std::vector<Geo
             if ((err = hipEventRecord(sc.e0, sc.s)) != hipSuccess) return err;
             for (int t = 0; t < T; ++t)
                 if ((err = heat3d7_ops.batch_launch(c.variant, c.tile, (const BatchProb *)d_probs,
-                                                    (const BatchItem *)d_items, n, t & 1, grid, nullptr, sc.s)) !=
+                                                    (const BatchItem *)d_items, n, t & 1, grid,
+                                                    sweeps_per_launch(c.variant), nullptr, sc.s)) !=
                     hipSuccess)
                     return err;
             if ((err = hipEventRecord(sc.e1, sc.s)) != hipSuccess) return err;
@@ -255,14 +256,15 @@ stencil_status capture(stencil_plan_s *p, void *const *fields, int T, hipStream_
         const BatchClass &C = b->classes[c];
         hipStream_t s = b->side[c];
         if ((e = hipStreamWaitEvent(s, b->evs[0], 0)) != hipSuccess) return abort_capture(e, "fork wait");
-        // a two-sweep class starts an odd sweep count with one single sweep
-        const int per = sweeps_per_launch(C.variant);
+        // a two-sweep class starts an odd sweep count with one single sweep; a
+        // three-sweep class starts with one launch of the remainder's sweeps
+        const int per = sweeps_per_launch(C.variant), rem = T % per;
         for (int t = 0; t < T;) {
-            const int v = (t == 0 && (T % per)) ? V_SATURATED : C.variant;
-            const int adv = sweeps_per_launch(v);
+            const int v = (t == 0 && rem && C.variant != V_SAT3) ? V_SATURATED : C.variant;
+            const int adv = (t == 0 && rem) ? (v == V_SAT3 ? rem : 1) : sweeps_per_launch(v);
             double *part = (t + adv == T) ? b->d_part + C.item_base : nullptr;
             if ((e = p->ops->batch_launch(v, C.tile, b->d_probs, b->d_items + C.item_base, C.n_items, launches[c] & 1,
-                                          C.grid, part, s)) != hipSuccess)
+                                          C.grid, adv, part, s)) != hipSuccess)
                 return abort_capture(e, "batch sweep");
             t += adv;
             ++launches[c];

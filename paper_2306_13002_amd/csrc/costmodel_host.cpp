@@ -214,16 +214,19 @@ bool load_model(std::vector<float> &model) {
 // The cost model's candidates: the exhaustive tuner's, the two-sweep form
 // included (feature 10 tells it apart, and the training campaign times it).
 std::vector<Cand> model_candidates(const KindOps *ops, int kind, const Geom &g, const TuneRequest &rq) {
-    // HEAT2D5's fused plain sweeps (tile.tz > 1) lie outside what the model was
-    // trained on; exhaustive tuning weighs them
+    // HEAT2D5's fused plain sweeps (tile.tz > 1) and the three-sweep form lie
+    // outside what the model was trained on; exhaustive tuning weighs them
     std::vector<Cand> c = tune_candidates(ops, kind, g, rq);
     c.erase(std::remove_if(c.begin(), c.end(),
-                           [kind](const Cand &x) { return kind == STENCIL_HEAT2D5 && x.tile.tz > 1; }),
+                           [kind](const Cand &x) {
+                               return (kind == STENCIL_HEAT2D5 && x.tile.tz > 1) || x.variant == V_SAT3;
+                           }),
             c.end());
     return c;
 }
 
 stencil_status tune_model(stencil_plan_s *p, const TuneRequest &rq, TuneEntry *best) {
+    if (rq.variant == V_SAT3) return fail(STENCIL_E_STATE, "the cost model does not rank the three-sweep form");
     std::vector<float> model;
     if (!load_model(model)) return fail(STENCIL_E_STATE, "no usable cost model at %s", model_path().c_str());
     const std::vector<Cand> cands = model_candidates(p->ops, p->kind, p->g, rq);

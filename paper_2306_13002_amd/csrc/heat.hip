@@ -451,6 +451,156 @@ __global__ __launch_bounds__((H3Sat2Shape<TX, TY>::NT)) void heat3d7_sat2(const 
     }
 }
 
+// Three sweeps per pass (SATURATED_T3): one thread per column of an RX x RY
+// region around the (RX - 4) x (RY - 4) output tile.  Sweep j (1..k, k <= 3
+// sweeps in this launch) runs on the region cells within k - j of the tile,
+// two planes behind sweep j - 1, so the value it needs from sweep j - 1 one
+// plane up was computed one step earlier, before the barrier that separates
+// the steps.  In-plane neighbours come from three-plane LDS rings (p^t with a
+// one-cell halo, then one ring per intermediate sweep); the column's centre
+// values from the thread's own registers (the p^t column it loads, and
+// per-sweep queues of its last three values).  Three slots suffice: a step
+// writes a plane two planes ahead of the one it reads, and the previous
+// step's reads are separated from this step's writes by the barrier.  Every
+// value is computed with heat3d7_sat_tile's operations, so a pass equals k
+// single-sweep launches bit for bit.  Dirichlet only.
+template <int RX, int RY>
+struct H3Sat3Shape {
+    static constexpr int K = 3, TX = RX - 2 * (K - 1), TY = RY - 2 * (K - 1), NT = RX * RY;
+    // row strides: odd numbers of doubles
+    static constexpr int LSP = RX + 3, PLP = (RY + 2) * LSP;  // p^t: the region and a one-cell halo
+    static constexpr int LSL = RX + 1, PLL = RY * LSL;        // intermediate sweeps: the region
+};
+
+// KK: the sweeps of this launch (3, or 1 or 2 for the remainder of a count),
+// a compile-time constant so that every sweep's participation test and
+// plane range fold.
+template <int RX, int RY, int KK>
+__device__ __forceinline__ double heat3d7_sat3_tile(const double *__restrict__ src, double *__restrict__ dst,
+                                                    const Geom &g, double cc, double cn, int zb, int bx, int by, int bz,
+                                                    double (*P)[H3Sat3Shape<RX, RY>::PLP],
+                                                    double (*Lv)[3][H3Sat3Shape<RX, RY>::PLL]) {
+    using S = H3Sat3Shape<RX, RY>;
+    constexpr int k = KK;
+    static_assert(KK >= 1 && KK <= S::K, "one to three sweeps per launch");
+    constexpr int K = S::K, TX = S::TX, TY = S::TY, LSP = S::LSP, LSL = S::LSL, NT = S::NT;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * RX + tx;
+    const int PX = g.nx + 2, PY = g.ny + 2;
+    const int xr0 = bx * TX + 1 - (K - 1), yr0 = by * TY + 1 - (K - 1);  // padded coords of region cell (0, 0)
+    const int X = xr0 + tx, Y = yr0 + ty;
+    const int dx = max(max(bx * TX + 1 - X, X - bx * TX - TX), 0);
+    const int dy = max(max(by * TY + 1 - Y, Y - by * TY - TY), 0);
+    const int d = max(dx, dy);  // distance of this column from the output tile
+    const bool col_ok = X >= 0 && X < PX && Y >= 0 && Y < PY;
+    const bool inxy = X >= 1 && X <= g.nx && Y >= 1 && Y <= g.ny;
+    const bool out_t = d == 0 && X <= g.nx && Y <= g.ny;
+    const long long col = col_ok ? (long long)Y * g.py + X : 0;
+    const int eP = (ty + 1) * LSP + tx + 1, eL = ty * LSL + tx;
+    const int k0 = bz * zb, k1 = min(k0 + zb, g.nz);  // output planes k0+1 .. k1 (padded)
+    const int hi0 = min(g.nz + 1, k1 + k);            // last p^t plane a sweep reads
+    HaloStager<double, RX, RY, 1, false, NT, LSP> halo;
+    halo.init(tid, xr0, yr0, g.py, PX, PY);
+    auto pin = [&](int z) { return z >= 0 && z <= hi0; };
+    auto ldp = [&](int z) { return (col_ok && pin(z)) ? src[col + (long long)z * g.pz] : 0.0; };
+    auto hload = [&](int z) {
+        if (pin(z)) {
+            halo.load(src + (long long)z * g.pz);
+        } else {
+#pragma unroll
+            for (int s = 0; s < decltype(halo)::HR; ++s) halo.val[s] = 0.0;
+        }
+    };
+    // step t runs sweep j at plane t - 2(j - 1); plane z sits in ring slot (z - t0) mod 3
+    const int t0 = k0 + 1 - (k - 1), tE = k1 + 2 * (k - 1);
+    double pm1 = ldp(t0 - 1), p0 = ldp(t0);
+    hload(t0);
+    P[0][eP] = p0;
+    halo.store(P[0]);
+    double cA = ldp(t0 + 1), cB = 0.0;
+    hload(t0 + 1);
+    double qa[K], qb[K], qc[K];  // sweep j's values at the last three steps (j = 1, 2 used)
+#pragma unroll
+    for (int j = 0; j < K; ++j) qa[j] = qb[j] = qc[j] = 0.0;
+    double acc = 0.0;
+    // u = (t - t0) mod 6: ring slots and the staging register are compile-time
+    auto step = [&](const int t, const int u, double &cur, double &nxt) {
+        P[(u + 1) % 3][eP] = cur;  // p^t plane t + 1, loaded one step earlier
+        halo.store(P[(u + 1) % 3]);
+        if (pin(t + 2)) {
+            nxt = ldp(t + 2);
+            halo.load(src + (long long)(t + 2) * g.pz);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = K; j >= 1; --j) {  // the last sweep first: each reads the queue before it advances
+            if (j > k) continue;
+            const int z = t - 2 * (j - 1);
+            const int sl = (u + 6 - 2 * (j - 1)) % 3;
+            const int lo = max(0, k0 + 1 - (k - j)), hi = min(g.nz + 1, k1 + (k - j));
+            if (d <= k - j && z >= lo && z <= hi) {
+                const double below = j == 1 ? pm1 : qc[j - 1];
+                const double centre = j == 1 ? p0 : qb[j - 1];
+                const double above = j == 1 ? cur : qa[j - 1];
+                double v = centre;
+                if (inxy && z >= 1 && z <= g.nz) {
+                    const double *o = j == 1 ? P[u % 3] : Lv[j - 2 < 0 ? 0 : j - 2][sl];
+                    const int e = j == 1 ? eP : eL, LS = j == 1 ? LSP : LSL;
+                    const double sm = ((o[e - 1] + o[e + 1]) + (o[e - LS] + o[e + LS])) + (below + above);
+                    v = fma(cn, sm, cc * centre);
+                }
+                if (j < k) {
+                    Lv[j - 1][sl][eL] = v;
+                    qc[j] = qb[j];
+                    qb[j] = qa[j];
+                    qa[j] = v;
+                } else if (out_t) {
+                    dst[col + (long long)z * g.pz] = v;
+                    const double dd = v - centre;
+                    acc = fma(dd, dd, acc);
+                }
+            } else if (j < k) {  // keep the queue aligned with the steps
+                qc[j] = qb[j];
+                qb[j] = qa[j];
+                qa[j] = 0.0;
+            }
+        }
+        pm1 = p0;
+        p0 = cur;
+    };
+    for (int t = t0;; t += 6) {
+        if (t > tE) break;
+        step(t, 0, cA, cB);
+        if (t + 1 > tE) break;
+        step(t + 1, 1, cB, cA);
+        if (t + 2 > tE) break;
+        step(t + 2, 2, cA, cB);
+        if (t + 3 > tE) break;
+        step(t + 3, 3, cB, cA);
+        if (t + 4 > tE) break;
+        step(t + 4, 4, cA, cB);
+        if (t + 5 > tE) break;
+        step(t + 5, 5, cB, cA);
+    }
+    return acc;
+}
+
+template <int RX, int RY, int KK>
+__global__ __launch_bounds__(RX *RY) void heat3d7_sat3(const double *__restrict__ src, double *__restrict__ dst,
+                                                       Geom g, double cc, double cn, int zb, int remap,
+                                                       double *__restrict__ part) {
+    using S = H3Sat3Shape<RX, RY>;
+    __shared__ double P[3][S::PLP];
+    __shared__ double Lv[2][3][S::PLL];
+    __shared__ double red[kMaxWaves];
+    int bx, by, bz;
+    tile_coords(remap, bx, by, bz);
+    const double acc = heat3d7_sat3_tile<RX, RY, KK>(src, dst, g, cc, cn, zb, bx, by, bz, P, Lv);
+    if (part) {
+        const double s = block_sum_f64(acc, red);
+        if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear_id()] = s;
+    }
+}
+
 // Work-list forms: each block walks items blockIdx.x, +gridDim.x, ... (the
 // batch launches one block per item up to 2^20 items) and runs the same tile
 // body as the single-problem kernel, so a batched problem is bit-identical to
@@ -488,6 +638,27 @@ __global__ __launch_bounds__((H3Sat2Shape<TX, TY>::NT)) void heat3d7_sat2_batch(
         const BatchProb &P = probs[w.prob];
         const double acc = heat3d7_sat2_tile<TX, TY>(P.f[parity], P.f[parity ^ 1], P.g, P.cc, P.cn, zb, w.bx, w.by,
                                                      w.bz, r0, r1);
+        if (part) {
+            const double s = block_sum_f64(acc, red);
+            if (threadIdx.x == 0 && threadIdx.y == 0) part[w.slot] = s;
+        }
+        __syncthreads();  // LDS is reused by the next item
+    }
+}
+
+template <int RX, int RY, int KK>
+__global__ __launch_bounds__(RX *RY) void heat3d7_sat3_batch(const BatchProb *__restrict__ probs,
+                                                             const BatchItem *__restrict__ items, int n_items,
+                                                             int parity, int zb, double *__restrict__ part) {
+    using S = H3Sat3Shape<RX, RY>;
+    __shared__ double P[3][S::PLP];
+    __shared__ double Lv[2][3][S::PLL];
+    __shared__ double red[kMaxWaves];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const BatchItem w = items[it];
+        const BatchProb &Q = probs[w.prob];
+        const double acc = heat3d7_sat3_tile<RX, RY, KK>(Q.f[parity], Q.f[parity ^ 1], Q.g, Q.cc, Q.cn, zb, w.bx,
+                                                         w.by, w.bz, P, Lv);
         if (part) {
             const double s = block_sum_f64(acc, red);
             if (threadIdx.x == 0 && threadIdx.y == 0) part[w.slot] = s;
@@ -567,9 +738,20 @@ hipError_t h2_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 #define HEAT3D7_SAT2_TILES(X) X(32, 4) X(32, 8) X(32, 16) X(32, 20) X(32, 24) X(32, 28) X(64, 4) X(64, 8) \
     X(128, 4)
 
+// Three-sweep regions (RX, RY): one thread per region column; the output
+// tile is (RX - 4) x (RY - 4).  Two blocks of the 32 x 32 region fit a CU's
+// LDS.
+#define HEAT3D7_SAT3_REGIONS(X) X(32, 32) X(32, 24) X(32, 16) X(64, 16)
+
 bool h3_tile_ok(int v, Tile t) {
     if (v == V_PLAIN) return plain_tile_ok(t);
     if (t.tz < 1) return false;
+    if (v == V_SAT3) {
+#define X(a, b) if (t.tx == a - 4 && t.ty == b - 4) return true;
+        HEAT3D7_SAT3_REGIONS(X)
+#undef X
+        return false;
+    }
     if (v == V_SAT2) {
 #define X(a, b) if (t.tx == a && t.ty == b) return true;
         HEAT3D7_SAT2_TILES(X)
@@ -598,6 +780,14 @@ int h3_sat2_tiles(Tile *out, int max) {
     return n;
 }
 
+int h3_sat3_tiles(Tile *out, int max) {
+    int n = 0;
+#define X(a, b) if (n < max) out[n++] = Tile{a - 4, b - 4, 0};
+    HEAT3D7_SAT3_REGIONS(X)
+#undef X
+    return n;
+}
+
 long long h3_nblocks(int v, Tile t, const Geom &g) {
     return cdiv(g.nx, t.tx) * cdiv(g.ny, t.ty) * cdiv(g.nz, t.tz);
 }
@@ -610,6 +800,25 @@ hipError_t h3_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(heat3d7_plain, grid, dim3(t.tx, t.ty, t.tz), 0, s, src, dst, a.g, a.c[0], a.c[1],
                            a.part);
         return hipGetLastError();
+    }
+    if (v == V_SAT3) {
+        if (a.sweeps < 1 || a.sweeps > 3) return hipErrorInvalidValue;
+#define X(A, B)                                                                                                \
+    if (t.tx == A - 4 && t.ty == B - 4) {                                                                      \
+        if (a.sweeps == 3)                                                                                     \
+            hipLaunchKernelGGL((heat3d7_sat3<A, B, 3>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.c[0], a.c[1], \
+                               t.tz, a.remap, a.part);                                                         \
+        else if (a.sweeps == 2)                                                                                \
+            hipLaunchKernelGGL((heat3d7_sat3<A, B, 2>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.c[0], a.c[1], \
+                               t.tz, a.remap, a.part);                                                         \
+        else                                                                                                   \
+            hipLaunchKernelGGL((heat3d7_sat3<A, B, 1>), grid, dim3(A, B, 1), 0, s, src, dst, a.g, a.c[0], a.c[1], \
+                               t.tz, a.remap, a.part);                                                         \
+        return hipGetLastError();                                                                              \
+    }
+        HEAT3D7_SAT3_REGIONS(X)
+#undef X
+        return hipErrorInvalidValue;
     }
     if (v == V_SAT2) {
 #define X(A, B)                                                                                              \
@@ -634,7 +843,26 @@ hipError_t h3_launch(int v, Tile t, const SweepArgs &a, hipStream_t s) {
 }
 
 hipError_t h3_batch_launch(int v, Tile t, const BatchProb *probs, const BatchItem *items, int n_items, int parity,
-                           int grid, double *part, hipStream_t s) {
+                           int grid, int sweeps, double *part, hipStream_t s) {
+    if (v == V_SAT3) {
+        if (sweeps < 1 || sweeps > 3) return hipErrorInvalidValue;
+#define X(A, B)                                                                                                 \
+    if (t.tx == A - 4 && t.ty == B - 4) {                                                                       \
+        if (sweeps == 3)                                                                                        \
+            hipLaunchKernelGGL((heat3d7_sat3_batch<A, B, 3>), dim3(grid), dim3(A, B, 1), 0, s, probs, items,    \
+                               n_items, parity, t.tz, part);                                                    \
+        else if (sweeps == 2)                                                                                   \
+            hipLaunchKernelGGL((heat3d7_sat3_batch<A, B, 2>), dim3(grid), dim3(A, B, 1), 0, s, probs, items,    \
+                               n_items, parity, t.tz, part);                                                    \
+        else                                                                                                    \
+            hipLaunchKernelGGL((heat3d7_sat3_batch<A, B, 1>), dim3(grid), dim3(A, B, 1), 0, s, probs, items,    \
+                               n_items, parity, t.tz, part);                                                    \
+        return hipGetLastError();                                                                               \
+    }
+        HEAT3D7_SAT3_REGIONS(X)
+#undef X
+        return hipErrorInvalidValue;
+    }
     if (v == V_PLAIN) {
         hipLaunchKernelGGL(heat3d7_plain_batch, dim3(grid), dim3(t.tx, t.ty, t.tz), 0, s, probs, items, n_items, parity,
                            part);
@@ -665,6 +893,6 @@ hipError_t h3_batch_launch(int v, Tile t, const BatchProb *probs, const BatchIte
 }  // namespace
 
 KindOps heat2d5_ops = {h2_tile_ok, nullptr, nullptr, h2_nblocks, h2_launch, nullptr};
-KindOps heat3d7_ops = {h3_tile_ok, h3_sat_tiles, h3_sat2_tiles, h3_nblocks, h3_launch, h3_batch_launch};
+KindOps heat3d7_ops = {h3_tile_ok, h3_sat_tiles, h3_sat2_tiles, h3_nblocks, h3_launch, h3_batch_launch, h3_sat3_tiles};
 
 }  // namespace stn

@@ -9,11 +9,12 @@ namespace stn {
 
 // Forms.  V_CSE_SAT, V_CSE_BULK and V_ACCSAT_POINT are the per-point forms of
 // the paper's ablation (rewritten arithmetic only, bulk load only, both);
-// V_SAT2 is the saturated form with two sweeps per pass (POISSON19, HEAT3D7).
-enum Variant { V_PLAIN = 0, V_SATURATED = 1, V_CSE_SAT = 3, V_CSE_BULK = 4, V_ACCSAT_POINT = 5, V_SAT2 = 6 };
+// V_SAT2 is the saturated form with two sweeps per pass (POISSON19, HEAT3D7),
+// V_SAT3 with three (HEAT3D7).
+enum Variant { V_PLAIN = 0, V_SATURATED = 1, V_CSE_SAT = 3, V_CSE_BULK = 4, V_ACCSAT_POINT = 5, V_SAT2 = 6, V_SAT3 = 7 };
 inline bool is_point_form(int v) { return v == V_CSE_SAT || v == V_CSE_BULK || v == V_ACCSAT_POINT; }
-// Sweeps one launch performs.
-inline int sweeps_per_launch(int v) { return v == V_SAT2 ? 2 : 1; }
+// Sweeps one full launch performs (a V_SAT3 launch may be asked for fewer).
+inline int sweeps_per_launch(int v) { return v == V_SAT2 ? 2 : (v == V_SAT3 ? 3 : 1); }
 
 // Launch shape.  Plain forms: block = (tx, ty, tz) threads, one per point.
 // Saturated forms: tx threads along x, a tile of ty rows, zblock planes
@@ -76,8 +77,10 @@ struct KindOps {
     // Persistent work-list sweep over a batch (nullptr: kind not batchable).
     // Items [0, n_items) are visited by `grid` blocks in a fixed stride; the
     // residual partial of item i goes to part[i] when part is non-null.
+    // sweeps: the sweeps this launch performs (V_SAT3: 1..3; others: their own).
     hipError_t (*batch_launch)(int variant, Tile t, const BatchProb *probs, const BatchItem *items, int n_items,
-                               int parity, int grid, double *part, hipStream_t s);
+                               int parity, int grid, int sweeps, double *part, hipStream_t s);
+    int (*sat3_tiles)(Tile *out, int max);  // output tiles of the three-sweep form; nullptr if none
 };
 
 extern KindOps heat2d5_ops, heat3d7_ops, poisson19_ops, wave25_ops, generic_ops;

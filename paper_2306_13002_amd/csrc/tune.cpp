@@ -114,6 +114,22 @@ std::vector<Cand> tune_candidates(const KindOps *ops, int kind, const Geom &g, c
                     if (!rq.tile_map || rq.tile_map == m) out.push_back({V_SAT2, t, m == 2 ? 1 : 0});
             }
     }
+    // the three-sweep form (HEAT3D7, Dirichlet)
+    if ((rq.variant == V_SAT3 || rq.variant == STENCIL_AUTO) && ops->sat3_tiles && rq.bc == STENCIL_BC_DIRICHLET) {
+        Tile st[16];
+        const int ns = ops->sat3_tiles(st, 16);
+        std::vector<int> zbs;
+        for (int zb : kZblocks)
+            if (zb < g.nz) zbs.push_back(zb);
+        zbs.push_back(g.nz);
+        for (int s = 0; s < ns; ++s)
+            for (int zb : zbs) {
+                Tile t{st[s].tx, st[s].ty, zb};
+                if (!ops->tile_ok(V_SAT3, t) || !tile_fits(t)) continue;
+                for (int m = 1; m <= 2; ++m)
+                    if (!rq.tile_map || rq.tile_map == m) out.push_back({V_SAT3, t, m == 2 ? 1 : 0});
+            }
+    }
     if (want_v(V_SATURATED) && ops->sat_tiles) {
         Tile st[64];
         const int ns = ops->sat_tiles(st, 64);
@@ -157,10 +173,10 @@ struct Buffers {
 
 std::string tune_key(const stencil_plan_s *p, const TuneRequest &rq) {
     char buf[512];
-    // "/c4": candidate set 4 (AUTO includes the two-sweep form, HEAT2D5 the
-    // fused plain sweeps with one-cell-per-thread tiles); entries of earlier
-    // sets are not reused
-    std::snprintf(buf, sizeof buf, "k%d/d%d/bc%d/n%dx%dx%d/r%d/py%lld/pz%lld/v%d/t%d,%d,%d,%d/h%08x/c4", p->kind,
+    // "/c5": candidate set 5 (AUTO includes the two- and three-sweep forms,
+    // HEAT2D5 the fused plain sweeps with one-cell-per-thread tiles); entries
+    // of earlier sets are not reused
+    std::snprintf(buf, sizeof buf, "k%d/d%d/bc%d/n%dx%dx%d/r%d/py%lld/pz%lld/v%d/t%d,%d,%d,%d/h%08x/c5", p->kind,
                   p->dtype, p->bc, p->g.nx, p->g.ny, p->g.nz, p->g.r, p->g.py, p->g.pz, rq.variant, rq.tile_x,
                   rq.tile_y, rq.zblock, rq.tile_map, p->taps_hash);
     return buf;

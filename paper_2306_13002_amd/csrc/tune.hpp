@@ -27,7 +27,7 @@ inline int launch_sweeps(int kind, int variant, const Tile &t) {
 }
 
 struct TuneEntry {
-    int variant;  // V_PLAIN, V_SATURATED or V_SAT2
+    int variant;  // V_PLAIN, V_SATURATED, V_SAT2 or V_SAT3
     Tile tile;
     int remap;    // 0 natural, 1 XCD-chunked
     double us;    // median time per sweep of the winner

@@ -20,7 +20,7 @@ STATUS_NAMES = {OK: "OK", E_INVAL: "E_INVAL", E_UNSUPPORTED: "E_UNSUPPORTED", E_
 KINDS = {"heat2d5": 1, "heat3d7": 2, "poisson19": 3, "wave25": 4, "generic": 5}
 DTYPES = {"f32": 1, "f64": 2}
 VARIANTS = {"plain": 0, "saturated": 1, "auto": 2, "cse_sat": 3, "cse_bulk": 4, "accsat_point": 5,
-            "saturated_t2": 6}
+            "saturated_t2": 6, "saturated_t3": 7}
 VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
 TUNES = {"fixed": 0, "exhaustive": 1, "model": 2}
 BCS = {"dirichlet": 0, "periodic": 1}

@@ -58,6 +58,9 @@ BAD = [
      "two-sweep"),
     (dict(kind="generic", n=(10, 10, 10), coef=(1.0,), taps=[(1, 0, 0)], cids=[0], radius=1, variant="saturated_t2"),
      S.E_UNSUPPORTED, "two-sweep"),
+    (dict(kind="poisson19", n=(10, 10, 10), variant="saturated_t3"), S.E_UNSUPPORTED, "three-sweep"),
+    (dict(kind="heat3d7", n=(10, 10, 10), coef=(0.4, 0.1), variant="saturated_t3", bc="periodic"), S.E_UNSUPPORTED,
+     "three-sweep"),
 ]
 
 

@@ -45,8 +45,9 @@ def single(n, u0, T, dev, **kw):
 
 @pytest.mark.parametrize("variant,tile", [("saturated", (32, 8, 8)), ("saturated", (64, 4, 16)),
                                           ("plain", (64, 4, 1)), ("plain", (128, 2, 1)),
-                                          ("saturated_t2", (32, 8, 8)), ("saturated_t2", (64, 4, 16))])
-@pytest.mark.parametrize("T", [3, 4])
+                                          ("saturated_t2", (32, 8, 8)), ("saturated_t2", (64, 4, 16)),
+                                          ("saturated_t3", (28, 28, 32)), ("saturated_t3", (60, 12, 8))])
+@pytest.mark.parametrize("T", [3, 4, 5])
 def test_batch_bitwise_equals_single(dev, variant, tile, T):
     from paper_2306_13002_amd.stencil import BatchPlan
     us, fs = fields_for(SIZES, dev)
@@ -152,6 +153,26 @@ def test_batch_two_sweep_tuned_workload(dev):
     for i in sorted(range(len(sizes)), key=lambda b: np.prod(sizes[b]))[:2]:
         want, _ = oracle.heat(us[i], 50, 0.4, 0.1)
         assert maxrel(inner(fs[i][0].cpu().numpy(), 1), inner(want, 1)) <= 1e-12
+
+
+def test_batch_three_sweep_equals_single_sweep_batch(dev):
+    """A batch whose classes run three sweeps per launch gives the
+    single-sweep batch's grids bit for bit (T not a multiple of three: one
+    launch of the remainder first); the residuals agree to rounding (the
+    forms sum different block partitions)."""
+    from paper_2306_13002_amd.stencil import BatchPlan
+    for T in (4, 5, 6):
+        out = []
+        for variant, tile in (("saturated", (64, 4, 16)), ("saturated_t3", (28, 12, 16))):
+            us, fs = fields_for(SIZES, dev)
+            bp = BatchPlan(SIZES, variant=variant, tile=tile)
+            bp.run(fs, iterations=T)
+            out.append(([f[0].cpu().numpy() for f in fs], bp.residuals()))
+            bp.close()
+        for a, b in zip(out[0][0], out[1][0]):
+            assert np.array_equal(a, b), T
+        for a, b in zip(out[0][1], out[1][1]):
+            assert abs(a - b) <= 1e-12 * a, T
 
 
 def test_batch_two_sweep_equals_single_sweep_batch(dev):

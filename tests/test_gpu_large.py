@@ -160,7 +160,7 @@ def test_wave25_beyond_2_31_elements(dev, variant):
     assert torch.equal(f[0][-4:], a[-4:]) and torch.equal(f[0][:, :, :4], a[:, :, :4])
 
 
-@pytest.mark.parametrize("variant", ["plain", "saturated", "saturated_t2"])
+@pytest.mark.parametrize("variant", ["plain", "saturated", "saturated_t2", "saturated_t3"])
 def test_tall_grids_beyond_65535_planes(dev, variant):
     """Thin columns taller than 65 535 planes: the plain kernels launch one
     block row per plane (a z grid dimension above 65 535), the saturated
@@ -178,6 +178,8 @@ def test_tall_grids_beyond_65535_planes(dev, variant):
     got = f[0].cpu().numpy()
     assert maxrel(got[1:-1, 1:-1, 1:-1], want[1:-1, 1:-1, 1:-1]) <= (0 if variant == "plain" else 1e-12)
     assert abs(gr - wr) <= 1e-10 * wr
+    if variant == "saturated_t3":  # a heat3d7 form only
+        return
     print(f"tall poisson19 {variant} n={n}", flush=True)
     pp, cf = synth.poisson19_random_inputs((n[2] + 2, n[1] + 2, n[0] + 2), seed=44)
     p = Plan("poisson19", n, variant=variant, omega=0.8, tune="fixed")

@@ -179,6 +179,55 @@ def test_heat3d7_two_sweep_equals_saturated_bitwise(dev, tile, zb, remap):
         assert gg == gr, T
 
 
+H3_SAT3_TILES = [(28, 28), (28, 20), (28, 12), (60, 12)]
+
+
+@pytest.mark.parametrize("tile", H3_SAT3_TILES)
+@pytest.mark.parametrize("zb", [1, 5, 64])
+@pytest.mark.parametrize("remap", ["natural", "xcd"])
+def test_heat3d7_three_sweep_equals_saturated_bitwise(dev, tile, zb, remap):
+    # three sweeps per pass (a remainder of one or two sweeps first): the grid
+    # equals single sweeps bit for bit; residuals to rounding (another tile)
+    u0 = synth.heat3d7_input(*N3, stream=6)
+    for T in (1, 2, 3, 4, 5, 7):
+        ref, gr = run_jacobi("heat3d7", u0, N3, dev, T, coef=(0.4, 0.1), variant="saturated", tile=(32, 8, 4))
+        got, gg = run_jacobi("heat3d7", u0, N3, dev, T, coef=(0.4, 0.1), variant="saturated_t3",
+                             tile=(tile[0], tile[1], zb), tile_map=remap)
+        assert np.array_equal(got, ref), T
+        assert abs(gg - gr) <= 1e-12 * gr, T
+
+
+@pytest.mark.parametrize("n", [(1, 1, 1), (3, 40, 2), (29, 29, 29), (61, 13, 7)])
+def test_heat3d7_three_sweep_small_grids(dev, n):
+    u0 = synth.heat3d7_input(*n, stream=8)
+    for T in (3, 4, 8):
+        want, wr = oracle.heat(u0, T, 0.4, 0.1)
+        got, gr = run_jacobi("heat3d7", u0, n, dev, T, coef=(0.4, 0.1), variant="saturated_t3", tile=(28, 12, 4))
+        assert maxrel(inner(got, 1), inner(want, 1)) <= 1e-12, T
+        assert np.array_equal(got[0], u0[0]) and np.array_equal(got[:, :, -1], u0[:, :, -1])
+        assert abs(gr - wr) <= 1e-10 * wr
+
+
+def test_heat3d7_three_sweep_vs_oracle(dev):
+    u0 = synth.heat3d7_input(*N3, stream=7)
+    want, wr = oracle.heat(u0, 9, 0.4, 0.1)
+    got, gr = run_jacobi("heat3d7", u0, N3, dev, 9, coef=(0.4, 0.1), variant="saturated_t3", tile=(28, 20, 8))
+    assert maxrel(inner(got, 1), inner(want, 1)) <= 1e-12
+    assert np.array_equal(got[0], u0[0]) and np.array_equal(got[:, :, -1], u0[:, :, -1])
+    assert abs(gr - wr) <= 1e-10 * wr
+
+
+def test_heat3d7_three_sweep_rules(dev):
+    # the default shape, and tiles outside the offered set refused
+    from paper_2306_13002_amd.stencil import E_UNSUPPORTED, StencilError
+    with Plan("heat3d7", (64, 64, 64), variant="saturated_t3", coef=(0.4, 0.1)) as p:
+        assert tuple(p.config()["tile"]) == (28, 28, 32)
+    for t in ((32, 8, 4), (28, 16, 4), (32, 32, 8)):
+        with pytest.raises(StencilError) as e:
+            Plan("heat3d7", (64, 64, 64), variant="saturated_t3", coef=(0.4, 0.1), tile=t)
+        assert e.value.status == E_UNSUPPORTED, t
+
+
 def test_heat3d7_two_sweep_vs_oracle(dev):
     u0 = synth.heat3d7_input(*N3, stream=7)
     want, wr = oracle.heat(u0, 6, 0.4, 0.1)
@@ -188,7 +237,7 @@ def test_heat3d7_two_sweep_vs_oracle(dev):
     assert abs(gr - wr) <= 1e-10 * wr
 
 
-@pytest.mark.parametrize("variant", ["plain", "saturated", "saturated_t2"])
+@pytest.mark.parametrize("variant", ["plain", "saturated", "saturated_t2", "saturated_t3"])
 def test_heat3d7_workload_full(dev, variant):
     """The 160^3 grid, T = 50, at the tuned launch shape the benchmark times."""
     n = (160, 160, 160)
@@ -447,6 +496,7 @@ def test_zero_iterations_and_state(dev):
 
 
 @pytest.mark.parametrize("kind,variant", [("heat3d7", "plain"), ("heat3d7", "saturated"), ("heat3d7", "saturated_t2"),
+                                          ("heat3d7", "saturated_t3"),
                                           ("wave25", "plain"), ("wave25", "saturated")])
 def test_pitched_layout(dev, kind, variant):
     # rows and planes padded beyond the grid: same result, gaps untouched

@@ -60,7 +60,8 @@ def _check_replays(p, f, init, coefs, T, other_T):
     return first
 
 
-@pytest.mark.parametrize("variant,T", [("plain", 4), ("saturated", 5), ("saturated_t2", 5), ("saturated_t2", 6)])
+@pytest.mark.parametrize("variant,T", [("plain", 4), ("saturated", 5), ("saturated_t2", 5), ("saturated_t2", 6),
+                                       ("saturated_t3", 5), ("saturated_t3", 6)])
 def test_heat3d7_replay(dev, variant, T):
     n = (45, 19, 23)
     u0 = synth.heat3d7_input(*n, stream=31)

@@ -34,7 +34,7 @@ def test_tuned_heat3d7_matches_oracle_and_caches(dev):
     u0 = synth.heat3d7_input(*n, stream=11)
     p = Plan("heat3d7", n, coef=(0.4, 0.1), tune="exhaustive")
     cfg = p.config()
-    assert cfg["variant"] in ("plain", "saturated", "saturated_t2")  # exhaustive AUTO weighs all three
+    assert cfg["variant"] in ("plain", "saturated", "saturated_t2", "saturated_t3")  # exhaustive AUTO weighs all four
     f = [torch.tensor(u0, device=dev), torch.full(u0.shape, float("nan"), dtype=torch.float64, device=dev)]
     p.run(f, iterations=4)
     got = f[0].cpu().numpy()

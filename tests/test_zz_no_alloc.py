@@ -77,10 +77,12 @@ CASES = [
     ("wave25", dict(variant="plain", coef=synth.WAVE25_COEF), _wave_case, (97, 70, 60), (40, 33, 21), 2),
     ("heat3d7", dict(variant="saturated_t2", coef=(0.4, 0.1)), _heat3_case, (130, 61, 77), (33, 20, 9), 5),
     ("heat3d7", dict(variant="saturated", coef=(0.4, 0.1)), _heat3_case, (130, 61, 77), (33, 20, 9), 4),
+    ("heat3d7", dict(variant="saturated_t3", coef=(0.4, 0.1)), _heat3_case, (130, 61, 77), (33, 20, 9), 5),
     ("poisson19", dict(variant="saturated_t2", omega=0.8), _p19_case, (127, 40, 66), (30, 11, 17), 3),
     ("poisson19", dict(variant="plain", omega=0.8), _p19_case, (127, 40, 66), (30, 11, 17), 2),
     ("heat2d5", dict(variant="plain", coef=(0.6, 0.1)), _heat2_case, (300, 211), (37, 29), 3),
     ("heat2d5", dict(variant="plain", coef=(0.6, 0.1), tile=(32, 32, 4)), _heat2_case, (300, 211), (37, 29), 7),
+    ("heat2d5", dict(variant="plain", coef=(0.6, 0.1), tile=(16, 16, 4)), _heat2_case, (300, 211), (37, 29), 7),
 ]
 
 
