@@ -178,11 +178,12 @@ def score(data, model_path, names=None):
 
 def tuner_gap(out_path=None):
     """Model tuning against exhaustive tuning where exhaustive tuning also
-    weighs the two-sweep form (poisson19 129x129x257, heat3d7 160^3 and
+    weighs the multi-sweep forms (poisson19 129x129x257, heat3d7 160^3 and
     400^3; AUTO form): each plan's chosen configuration is timed the same
-    way (median of 5 runs of 4 sweeps, HIP events) and the ratio reported.
-    Both tuners weigh all three forms (the model tells them apart by its
-    form feature)."""
+    way (median of 5 runs of 6 sweeps, HIP events) and the ratio reported.
+    Both tuners weigh plain, saturated and two-sweep (the model tells them
+    apart by its form feature); only exhaustive tuning weighs the heat3d7
+    three-sweep form, which lies outside the model's training set."""
     import torch
     dev = torch.device("cuda:0")
     rows = []
@@ -198,10 +199,10 @@ def tuner_gap(out_path=None):
         for tune in ("model", "exhaustive"):
             p = S.Plan(kind, n, variant="auto", tune=tune, **kw)
             p.profile(True)
-            p.run(fields, coefs, iterations=4)
+            p.run(fields, coefs, iterations=6)
             ts = []
             for _ in range(5):
-                p.run(fields, coefs, iterations=4)
+                p.run(fields, coefs, iterations=6)
                 ms, k = p.profile_read()
                 ts.append(ms / k)
             res[tune] = {"config": p.config(), "us_per_sweep": float(np.median(ts)) * 1e3}
