@@ -127,7 +127,7 @@ typedef enum { STENCIL_F32 = 1, STENCIL_F64 = 2 } stencil_dtype; /* storage type
  * Bit-identical to SATURATED at the same tile, z-block and tile map (an odd
  * sweep count starts with one SATURATED sweep).  EXHAUSTIVE and MODEL tuning
  * of AUTO consider it beside PLAIN and SATURATED (the model's form feature
- * tells the three apart; its target is the time per sweep in every form).
+ * tells the forms apart; its target is the time per sweep in every form).
  *
  * SATURATED_T3 (HEAT3D7, Dirichlet; single and batched plans): three sweeps
  * per pass, one thread per column of a region two cells wider on every side
@@ -135,9 +135,8 @@ typedef enum { STENCIL_F32 = 1, STENCIL_F64 = 2 } stencil_dtype; /* storage type
  * the first and second sweeps are recomputed on the ring, and every input
  * stream is read once per three sweeps.  Bit-identical to SATURATED (a sweep
  * count that is not a multiple of three starts with one launch of the
- * remainder's sweeps in the same form).  EXHAUSTIVE tuning of AUTO weighs
- * it; MODEL tuning leaves it out (outside the model's training set) and,
- * asked for it with the shape open, tunes exhaustively. */
+ * remainder's sweeps in the same form).  EXHAUSTIVE and MODEL tuning of AUTO
+ * weigh it (the model's form feature tells the four forms apart). */
 typedef enum {
     STENCIL_PLAIN = 0,
     STENCIL_SATURATED = 1,

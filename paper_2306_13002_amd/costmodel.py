@@ -7,7 +7,7 @@
 collect: for the fixed workloads (heat2d5 256^2, poisson19 129x129x257,
 wave25 512^3, heat3d7 160^3 and 400^3) and the seeded generic corpus
 (stencils 0..249 on their drawn 64..512 grid edges; --cap N caps the edges),
-time every candidate the tuners consider, the two-sweep form included --
+time every candidate the tuners consider, the multi-sweep forms included --
 median of 3 runs after a warm-up, HIP events through the library's profiling
 hook, seconds per sweep -- and store its 24 features (computed by the
 library) with log(seconds per sweep).  Stencils 0..199 and the fixed
@@ -81,7 +81,7 @@ def time_candidate(kind, n, kw, cand, fields, coefs, torch, reps=3):
     v, tile, m = cand
     p = S.Plan(kind, n, variant=v, tile=tile, tile_map=m, **kw)
     p.profile(True)
-    it = 2 if v == "saturated_t2" else 1  # one launch of the form (an odd count would start single-sweep)
+    it = {"saturated_t2": 2, "saturated_t3": 3}.get(v, 1)  # one launch of the form (a remainder would add a launch)
     p.run(fields, coefs, iterations=it)
     ts = []
     for _ in range(reps):
@@ -181,9 +181,8 @@ def tuner_gap(out_path=None):
     weighs the multi-sweep forms (poisson19 129x129x257, heat3d7 160^3 and
     400^3; AUTO form): each plan's chosen configuration is timed the same
     way (median of 5 runs of 6 sweeps, HIP events) and the ratio reported.
-    Both tuners weigh plain, saturated and two-sweep (the model tells them
-    apart by its form feature); only exhaustive tuning weighs the heat3d7
-    three-sweep form, which lies outside the model's training set."""
+    Both tuners weigh every form (the model tells them apart by its form
+    feature)."""
     import torch
     dev = torch.device("cuda:0")
     rows = []

@@ -65,11 +65,13 @@ StencilInfo stencil_info(const stencil_desc *d, const Geom &g) {
 //  0 XCD-chunked tile map   1 radius            2 fraction of off-axis taps
 //  3 taps                   4 distinct coefs    5 bytes per element
 //  6-8 log2 nx, ny, nz      9 log2 points      10 form: 0 plain, 1 saturated,
-//                                                 2 saturated, two sweeps per pass
+//                                                 2 saturated, two sweeps per pass,
+//                                                 3 saturated, three sweeps per pass
 // 11-13 log2 tile x, y, z  14 read-footprint ratio of a tile incl. halo
 // 15 LDS bytes per block   16 estimated VGPRs  17 estimated waves per SIMD
-// 18 algorithmic bytes per point and sweep (halved by two sweeps per pass)
-// 19 flops/pt of the form (two sweeps per pass: with the recomputed ring)
+// 18 algorithmic bytes per point and sweep (halved by two sweeps per pass,
+//    a third of it by three)
+// 19 flops/pt of the form (several sweeps per pass: with the recomputed rings)
 // 20 arithmetic intensity
 // 21 the paper's static cost of the form's per-point expression (Sec. Cost
 //    Model: constants 0, inputs 1, operations 10, memory accesses 100)
@@ -77,8 +79,8 @@ StencilInfo stencil_info(const stencil_desc *d, const Geom &g) {
 // The target the model learns is log(seconds per sweep) in every form.
 void cost_features(const StencilInfo &si, const Cand &c, float out[24]) {
     const int r = si.r, tx = c.tile.tx, ty = c.tile.ty, tz = c.tile.tz;
-    const bool t2 = c.variant == V_SAT2;
-    const bool sat = c.variant == V_SATURATED || t2;
+    const bool t2 = c.variant == V_SAT2, t3 = c.variant == V_SAT3;
+    const bool sat = c.variant == V_SATURATED || t2 || t3;
     const double pts = (double)si.g.nx * si.g.ny * si.g.nz;
     double bytes_pt, flops, loads, ops, inputs, lds = 0, vgpr, blocks;
     switch (si.kind) {
@@ -135,12 +137,24 @@ void cost_features(const StencilInfo &si, const Cand &c, float out[24]) {
         lds = 4.0 * eb * ((ty + 4.0) * (tx + 5.0) + (ty + 2.0) * (tx + 3.0));
         vgpr = si.kind == STENCIL_POISSON19 ? 158 : 56;
     }
+    // three sweeps per pass (HEAT3D7): one thread per column of a region two
+    // cells wider than the tile on every side; sweeps 1 and 2 recomputed on
+    // rings of two and one cells; three-plane rings of the state (region and a
+    // one-cell halo) and of the two intermediate sweeps (the region)
+    if (t3) {
+        const double rx = tx + 4.0, ry = ty + 4.0;
+        ring1 = rx * ry / ((double)tx * ty);
+        bytes_pt /= 3.0;
+        flops *= (rx * ry + (tx + 2.0) * (ty + 2.0) + (double)tx * ty) / (3.0 * tx * ty);
+        lds = 3.0 * 8 * ((ry + 2) * (rx + 3) + 2 * ry * (rx + 1));
+        vgpr = 56;
+    }
     blocks = std::ceil((double)si.g.nx / tx) * std::ceil((double)si.g.ny / ty) * std::ceil((double)si.g.nz / tz);
-    const double threads = (double)tx * ty * (sat ? (t2 ? ring1 : 1.0) : tz);
+    const double threads = (double)tx * ty * (sat ? ((t2 || t3) ? ring1 : 1.0) : tz);
     const double wpb = std::ceil(threads / 64);
     double waves = std::min(8.0, std::floor(512.0 / vgpr));
     if (lds > 0) waves = std::min(waves, std::floor(160.0 * 1024 / lds) * wpb / 4);
-    const int rf = t2 ? 2 * r : r;
+    const int rf = t3 ? 3 * r : (t2 ? 2 * r : r);
     const double foot = sat ? (double)(tx + 2 * rf) * (ty + 2 * rf) / ((double)tx * ty)
                             : (double)(tx + 2 * r) * (ty + 2 * r) * (tz + 2 * r) / ((double)tx * ty * tz);
     const double ws = (si.kind == STENCIL_POISSON19 ? 14.0 * 4 : (si.kind == STENCIL_WAVE25 ? 3.0 * 8 : 2.0 * si.eb)) *
@@ -148,7 +162,7 @@ void cost_features(const StencilInfo &si, const Cand &c, float out[24]) {
     const double cost = 100.0 * (loads + 1) + 10.0 * ops + 1.0 * inputs;
     const double f[24] = {(double)(sat && c.remap), (double)r, si.box_frac, (double)si.n_taps, (double)si.n_coef,
                           (double)si.eb, std::log2((double)si.g.nx), std::log2((double)si.g.ny),
-                          std::log2((double)si.g.nz), std::log2(pts), t2 ? 2.0 : (double)sat, std::log2((double)tx),
+                          std::log2((double)si.g.nz), std::log2(pts), t3 ? 3.0 : (t2 ? 2.0 : (double)sat), std::log2((double)tx),
                           std::log2((double)ty), std::log2((double)tz), foot, lds, vgpr, waves, bytes_pt, flops,
                           flops / bytes_pt, cost, ws / (256.0 * 1024 * 1024), blocks / 256.0};
     for (int i = 0; i < 24; ++i) out[i] = (float)f[i];
@@ -211,22 +225,20 @@ bool load_model(std::vector<float> &model) {
 
 }  // namespace
 
-// The cost model's candidates: the exhaustive tuner's, the two-sweep form
-// included (feature 10 tells it apart, and the training campaign times it).
+// The cost model's candidates: the exhaustive tuner's, the two- and
+// three-sweep forms included (feature 10 tells them apart, and the training
+// campaign times them).
 std::vector<Cand> model_candidates(const KindOps *ops, int kind, const Geom &g, const TuneRequest &rq) {
-    // HEAT2D5's fused plain sweeps (tile.tz > 1) and the three-sweep form lie
-    // outside what the model was trained on; exhaustive tuning weighs them
+    // HEAT2D5's fused plain sweeps (tile.tz > 1) lie outside what the model was
+    // trained on; exhaustive tuning weighs them
     std::vector<Cand> c = tune_candidates(ops, kind, g, rq);
     c.erase(std::remove_if(c.begin(), c.end(),
-                           [kind](const Cand &x) {
-                               return (kind == STENCIL_HEAT2D5 && x.tile.tz > 1) || x.variant == V_SAT3;
-                           }),
+                           [kind](const Cand &x) { return kind == STENCIL_HEAT2D5 && x.tile.tz > 1; }),
             c.end());
     return c;
 }
 
 stencil_status tune_model(stencil_plan_s *p, const TuneRequest &rq, TuneEntry *best) {
-    if (rq.variant == V_SAT3) return fail(STENCIL_E_STATE, "the cost model does not rank the three-sweep form");
     std::vector<float> model;
     if (!load_model(model)) return fail(STENCIL_E_STATE, "no usable cost model at %s", model_path().c_str());
     const std::vector<Cand> cands = model_candidates(p->ops, p->kind, p->g, rq);
@@ -282,7 +294,8 @@ stencil_status stencil_features(const stencil_desc *d, int32_t variant, int32_t 
     int rz = 0;
     stencil_status st = validate_desc(d, g, rz);
     if (st != STENCIL_OK) return st;
-    if ((variant != V_PLAIN && variant != V_SATURATED && variant != V_SAT2) || tile_x < 1 || tile_y < 1 || zblock < 1 ||
+    if ((variant != V_PLAIN && variant != V_SATURATED && variant != V_SAT2 && variant != V_SAT3) || tile_x < 1 ||
+        tile_y < 1 || zblock < 1 ||
         (tile_map != 1 && tile_map != 2))
         return fail(STENCIL_E_INVAL, "bad candidate");
     cost_features(stencil_info(d, g), Cand{variant, Tile{tile_x, tile_y, zblock}, tile_map == 2}, out);

@@ -35,13 +35,17 @@ def test_paper_static_cost_feature():
 def test_two_sweep_form_is_a_model_candidate_with_its_own_features():
     n, kw = (160, 160, 160), dict(coef=(0.4, 0.1))
     c = S.candidates("heat3d7", n, **kw)
-    assert {v for v, _, _ in c} == {"plain", "saturated", "saturated_t2"}
+    assert {v for v, _, _ in c} == {"plain", "saturated", "saturated_t2", "saturated_t3"}
     t = (32, 16, 16)
     one = S.features("heat3d7", n, ("saturated", t, "xcd"), **kw)
     two = S.features("heat3d7", n, ("saturated_t2", t, "xcd"), **kw)
     assert one[10] == 1.0 and two[10] == 2.0
     assert two[18] == one[18] / 2  # one pass over memory serves two sweeps
     assert two[14] > one[14]      # the two-cell ring of the state tile
+    three = S.features("heat3d7", n, ("saturated_t3", (28, 20, 16), "xcd"), **kw)
+    assert three[10] == 3.0 and abs(three[18] - one[18] / 3) < 1e-6  # one pass serves three sweeps
+    assert three[19] > one[19]  # sweeps 1 and 2 recomputed on their rings
     p19 = S.candidates("poisson19", (127, 127, 255), omega=0.8)
     assert "saturated_t2" in {v for v, _, _ in p19}
     assert all(v != "saturated_t2" for v, _, _ in S.candidates("wave25", (64, 64, 64), coef=synth.WAVE25_COEF))
+    assert "saturated_t3" not in {v for v, _, _ in p19}  # a heat3d7 form only
