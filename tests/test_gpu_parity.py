@@ -118,6 +118,30 @@ def test_heat2d5_fused_sweeps_write_the_scratch_ring(dev, n, tile, T):
     assert np.array_equal(a, want)
 
 
+@pytest.mark.parametrize("tile", [(64, 4, 1), (16, 16, 5), (12, 12, 10), (32, 32, 6)])
+def test_heat2d5_pitched_rows(dev, tile):
+    # rows padded beyond the grid (row pitch 301 > 258): one launch per sweep
+    # and both fused kernels equal the oracle bit for bit, the gaps untouched
+    n, T = (256, 61), 11
+    PX, PY, py = n[0] + 2, n[1] + 2, 301
+    u0 = synth.heat2d5_input(n[0], ny=n[1])
+    want, wr = oracle.heat(u0, T, 0.6, 0.1)
+    buf = np.full(PY * py, -7.0)
+    for y in range(PY):
+        buf[y * py: y * py + PX] = u0[y]
+    p = Plan("heat2d5", n, variant="plain", coef=(0.6, 0.1), tile=tile, pitch=(py, 0))
+    f = [_dev(buf, dev), torch.full((PY * py,), float("nan"), dtype=torch.float64, device=dev)]
+    p.run(f, iterations=T)
+    gr = p.residual()
+    p.close()
+    out = f[0].cpu().numpy()
+    got = np.stack([out[y * py: y * py + PX] for y in range(PY)])
+    assert np.array_equal(got, want)
+    gaps = np.concatenate([out[y * py + PX: (y + 1) * py] for y in range(PY - 1)])
+    assert np.all(gaps == -7.0)
+    assert abs(gr - wr) <= 1e-10 * wr
+
+
 def test_heat2d5_fused_sweeps_rules(dev):
     # zblock alone picks the 32 x 32 fused tile; periodic boundaries and
     # tiles outside the offered set are refused before anything runs
