@@ -116,6 +116,26 @@ def test_batch_class_tuning_cache_roundtrip(tmp_path):
     assert len(cache.read_text().strip().splitlines()) == 2
 
 
+@pytest.mark.parametrize("tune", ["exhaustive", "model"])
+def test_tuned_three_sweep_heat3d7(dev, tune):
+    """Both tuners, asked for the three-sweep form with the shape open, pick
+    one of its tiles; the tuned run matches the oracle (T = 7: a one-sweep
+    launch, then two three-sweep passes)."""
+    from paper_2306_13002_amd.stencil import Plan
+    n = (61, 35, 47)
+    u0 = synth.heat3d7_input(*n, stream=12)
+    p = Plan("heat3d7", n, variant="saturated_t3", coef=(0.4, 0.1), tune=tune)
+    cfg = p.config()
+    assert cfg["variant"] == "saturated_t3"
+    assert tuple(cfg["tile"][:2]) in [(28, 28), (28, 20), (28, 12), (60, 12)]
+    f = [torch.tensor(u0, device=dev), torch.full(u0.shape, float("nan"), dtype=torch.float64, device=dev)]
+    p.run(f, iterations=7)
+    want, wr = oracle.heat(u0, 7, 0.4, 0.1)
+    assert maxrel(inner(f[0].cpu().numpy(), 1), inner(want, 1)) <= 1e-12
+    assert abs(p.residual() - wr) <= 1e-10 * wr
+    p.close()
+
+
 def test_tuned_two_sweep_poisson19(dev):
     """The two-sweep form's tuned pick is one of its own shapes and its result
     equals the single-sweep form at that shape."""
