@@ -109,7 +109,8 @@ typedef enum {
 
 typedef enum { STENCIL_F32 = 1, STENCIL_F64 = 2 } stencil_dtype; /* storage type */
 /* PLAIN and SATURATED are the two forms (see the top of this file); AUTO lets
- * the plan choose between them.  The per-point ablation forms of the paper's
+ * the plan choose between them and, where a kind offers them, the multi-sweep
+ * saturated forms below (FIXED tuning: SATURATED).  The per-point ablation forms of the paper's
  * evaluation (Sec. Evaluation: CSE, CSE+SAT, CSE+BULK, ACCSAT) exist for WAVE25
  * and POISSON19, one thread per point with every operand from memory (CSE is
  * PLAIN: no address is loaded twice in these bodies):
