@@ -479,7 +479,7 @@ def mlp_predict(model, X, stream=None):
     return out
 
 
-# ---------------------------------------------------------------- streaming probe
+# ---------------------------------------------------------------- streaming kernels of known traffic
 STREAM_OPS = {"copy": 0, "3r1w": 1}
 
 
